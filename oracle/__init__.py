@@ -1,0 +1,241 @@
+"""CPU oracle of the APRIL intermediate filter -- TEST INFRASTRUCTURE ONLY.
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The GPU library never calls it and shares no code with it.
+The arithmetic lives in oracle.c (plain C, built with gcc); this module only
+marshals numpy arrays in and out.
+
+Functions (each follows the paper passage named in oracle.c):
+    hilbert(order, x, y)              Hilbert position of cells (Sec. 3.2)
+    classify(grid, poly)              per-cell Full/Partial/Empty (Sec. 4.1)
+    build_lists(grid, polys)          A- and F-lists (Sec. 4.1)
+    interval_join(X, Y)               IntervalJoin of Alg. 2
+    filter_pairs(LR, LS, r, s)        Alg. 2 verdicts + bytes moved per pair
+    mbr_join(R, S)                    candidate pairs (closed MBRs meet)
+    polygons_intersect(a, b)          exact closed-polygon intersection
+    twice_area(poly)                  exact shoelace area x2 (lattice units^2)
+
+Parity is pinned for every function by tests/test_oracle_*.py against
+closed forms, brute force and invariants; see those files.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+TN, TH, IND = 0, 1, 2
+EMPTY, PARTIAL, FULL = 0, 1, 2
+
+
+def build() -> str:
+    """Compile oracle.c into liboracle.so with gcc (always recompiles)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC", "-pthread",
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    L = C.CDLL(_LIB)
+    P = C.c_void_p
+    i64, u64, i32, d = C.c_int64, C.c_uint64, C.c_int, C.c_double
+    L.orc_hilbert.restype = u64
+    L.orc_hilbert.argtypes = [i32, u64, u64]
+    L.orc_hilbert_many.argtypes = [i32, P, P, i64, P]
+    L.orc_classify.argtypes = [d, d, d, i32, P, i64, C.POINTER(P), C.POINTER(i64)]
+    L.orc_free.argtypes = [P]
+    L.orc_build.argtypes = [d, d, d, i32, P, P, i64, i32, C.POINTER(P)]
+    L.orc_lists_sizes.argtypes = [P, C.POINTER(i64), C.POINTER(i64)]
+    L.orc_lists_export.argtypes = [P] * 7
+    L.orc_lists_free.argtypes = [P]
+    L.orc_interval_join.argtypes = [P, P, u64, P, P, u64, C.POINTER(u64), C.POINTER(u64)]
+    L.orc_filter.argtypes = [P] * 14 + [i64, P, P, i32]
+    L.orc_mbr_join.argtypes = [P, P, i64, P, P, i64, i32, C.POINTER(P), C.POINTER(i64)]
+    L.orc_pairs_export.argtypes = [P, P, P]
+    L.orc_pairs_free.argtypes = [P]
+    L.orc_polygons_intersect.argtypes = [P, i64, P, i64]
+    L.orc_twice_area.argtypes = [P, i64, C.POINTER(i64), C.POINTER(u64)]
+    _lib = L
+    return L
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc < 0:
+        raise OracleError({-1: "invalid input", -2: "outside the grid / guard ring",
+                           -3: "out of memory"}.get(rc, str(rc)))
+    return rc
+
+
+def _grid_args(grid):
+    x0, y0, side, order = grid.as_tuple() if hasattr(grid, "as_tuple") else grid
+    return float(x0), float(y0), float(side), int(order)
+
+
+def default_threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def hilbert(order: int, x, y) -> np.ndarray:
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.uint64).ravel())
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.uint64).ravel())
+    out = np.empty(len(x), dtype=np.uint64)
+    _load().orc_hilbert_many(order, _p(x), _p(y), len(x), _p(out))
+    return out
+
+
+def classify(grid, xy: np.ndarray) -> np.ndarray:
+    """[k, 3] int64 rows (i, j, class) over the polygon's cell window."""
+    L = _load()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    ptr = C.c_void_p()
+    n = C.c_int64()
+    _check(L.orc_classify(*_grid_args(grid), _p(xy), len(xy), C.byref(ptr), C.byref(n)))
+    try:
+        buf = (C.c_int64 * (3 * n.value)).from_address(ptr.value) if n.value else []
+        out = np.array(buf, dtype=np.int64).reshape(-1, 3)
+    finally:
+        L.orc_free(ptr)
+    return out
+
+
+@dataclass
+class Lists:
+    """A- and F-lists of a collection: CSR offsets + SoA uint32 endpoints."""
+
+    offA: np.ndarray
+    sA: np.ndarray
+    eA: np.ndarray
+    offF: np.ndarray
+    sF: np.ndarray
+    eF: np.ndarray
+
+    def __len__(self):
+        return len(self.offA) - 1
+
+    def A(self, k):
+        a, b = int(self.offA[k]), int(self.offA[k + 1])
+        return self.sA[a:b], self.eA[a:b]
+
+    def F(self, k):
+        a, b = int(self.offF[k]), int(self.offF[k + 1])
+        return self.sF[a:b], self.eF[a:b]
+
+
+def build_lists(grid, polys, nthreads: int = 0) -> Lists:
+    L = _load()
+    xy = np.ascontiguousarray(polys.xy, dtype=np.float64)
+    voff = np.ascontiguousarray(polys.voff, dtype=np.int64)
+    n = len(voff) - 1
+    h = C.c_void_p()
+    _check(L.orc_build(*_grid_args(grid), _p(xy), _p(voff), n, nthreads or default_threads(),
+                       C.byref(h)))
+    try:
+        na, nf = C.c_int64(), C.c_int64()
+        L.orc_lists_sizes(h, C.byref(na), C.byref(nf))
+        out = Lists(np.empty(n + 1, np.uint64), np.empty(na.value, np.uint32),
+                    np.empty(na.value, np.uint32), np.empty(n + 1, np.uint64),
+                    np.empty(nf.value, np.uint32), np.empty(nf.value, np.uint32))
+        L.orc_lists_export(h, _p(out.offA), _p(out.sA), _p(out.eA), _p(out.offF),
+                           _p(out.sF), _p(out.eF))
+    finally:
+        L.orc_lists_free(h)
+    return out
+
+
+def interval_join(X, Y):
+    """(overlap?, elements of X read, elements of Y read) -- Alg. 2 IntervalJoin."""
+    xs = np.ascontiguousarray(X[0], dtype=np.uint32)
+    xe = np.ascontiguousarray(X[1], dtype=np.uint32)
+    ys = np.ascontiguousarray(Y[0], dtype=np.uint32)
+    ye = np.ascontiguousarray(Y[1], dtype=np.uint32)
+    rx, ry = C.c_uint64(), C.c_uint64()
+    hit = _load().orc_interval_join(_p(xs), _p(xe), len(xs), _p(ys), _p(ye), len(ys),
+                                    C.byref(rx), C.byref(ry))
+    return bool(hit), rx.value, ry.value
+
+
+def filter_pairs(LR: Lists, LS: Lists, r, s, nthreads: int = 0, want_bytes=False):
+    """Alg. 2 over candidate pairs; returns verdicts (uint8) [and bytes moved]."""
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    s = np.ascontiguousarray(s, dtype=np.uint32)
+    assert len(r) == len(s)
+    if len(r):
+        assert int(r.max()) < len(LR) and int(s.max()) < len(LS)
+    v = np.empty(len(r), np.uint8)
+    b = np.empty(len(r), np.uint64) if want_bytes else None
+    _load().orc_filter(_p(LR.offA), _p(LR.sA), _p(LR.eA), _p(LR.offF), _p(LR.sF), _p(LR.eF),
+                       _p(LS.offA), _p(LS.sA), _p(LS.eA), _p(LS.offF), _p(LS.sF), _p(LS.eF),
+                       _p(r), _p(s), len(r), _p(v), _p(b) if b is not None else None,
+                       nthreads or default_threads())
+    return (v, b) if want_bytes else v
+
+
+def filter_pairs_timed(LR: Lists, LS: Lists, r, s, nthreads: int):
+    """Like filter_pairs; returns (verdicts, threads used) for timing runs."""
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    s = np.ascontiguousarray(s, dtype=np.uint32)
+    v = np.empty(len(r), np.uint8)
+    used = _load().orc_filter(_p(LR.offA), _p(LR.sA), _p(LR.eA), _p(LR.offF), _p(LR.sF),
+                              _p(LR.eF), _p(LS.offA), _p(LS.sA), _p(LS.eA), _p(LS.offF),
+                              _p(LS.sF), _p(LS.eF), _p(r), _p(s), len(r), _p(v), None, nthreads)
+    return v, used
+
+
+def mbr_join(R, S, nthreads: int = 0):
+    """All (r, s) with intersecting closed MBRs, sorted by (r, s)."""
+    L = _load()
+    xr = np.ascontiguousarray(R.xy, dtype=np.float64)
+    xs = np.ascontiguousarray(S.xy, dtype=np.float64)
+    vr = np.ascontiguousarray(R.voff, dtype=np.int64)
+    vs = np.ascontiguousarray(S.voff, dtype=np.int64)
+    h = C.c_void_p()
+    n = C.c_int64()
+    rc = L.orc_mbr_join(_p(xr), _p(vr), len(vr) - 1, _p(xs), _p(vs), len(vs) - 1,
+                        nthreads or default_threads(), C.byref(h), C.byref(n))
+    try:
+        _check(rc)
+        r = np.empty(n.value, np.uint32)
+        s = np.empty(n.value, np.uint32)
+        L.orc_pairs_export(h, _p(r), _p(s))
+    finally:
+        L.orc_pairs_free(h)
+    return r, s
+
+
+def polygons_intersect(a: np.ndarray, b: np.ndarray) -> bool:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    return bool(_check(_load().orc_polygons_intersect(_p(a), len(a), _p(b), len(b))))
+
+
+def twice_area(xy: np.ndarray) -> int:
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    hi, lo = C.c_int64(), C.c_uint64()
+    _load().orc_twice_area(_p(xy), len(xy), C.byref(hi), C.byref(lo))
+    return (hi.value << 64) + lo.value

@@ -1,0 +1,219 @@
+/*
+ * april.h -- C ABI of the MI355X APRIL intermediate filter.
+ *
+ * APRIL (Georgiadis, Tzirita Zacharatou, Mamoulis, "Raster Interval Object
+ * Approximations for Spatial Intersection Joins") approximates every polygon
+ * by two sorted lists of Hilbert-ordered cell intervals on one global
+ * 2^N x 2^N grid: the A-list (every cell the polygon touches) and the F-list
+ * (every cell it fully covers) (Sec. 4.1).  For a candidate pair (r, s) left
+ * by an MBR filter, three merge-joins decide (Sec. 4.2, Alg. 2):
+ *   A(r) x A(s) empty                        -> true negative (APRIL_TN)
+ *   A(r) x F(s) or F(r) x A(s) non-empty     -> true hit      (APRIL_TH)
+ *   otherwise                                -> indecisive    (APRIL_INDECISIVE)
+ *
+ * Conventions
+ *   - Coordinates are float64 multiples of 2^-30 ("the lattice"); the grid
+ *     origin is a lattice point and the cell side an integer number of
+ *     lattice units, so all geometry is decided exactly in integers.
+ *   - Cell (i, j) is the closed square [x0 + i w, x0 + (i+1) w] x
+ *     [y0 + j w, y0 + (j+1) w]; a cell is in the A-list iff the closed cell
+ *     meets the closed polygon, in the F-list iff it lies inside it.  (The
+ *     paper defines the classes by covered fraction, 0 / partial / 100 %;
+ *     closed sets make touching polygons share a cell, so true negatives and
+ *     true hits stay exact for polygons that only touch.)
+ *   - Intervals are half-open [start, end) of Hilbert positions, uint32.
+ *   - Pointers named d_* are device (HBM) pointers; all others are host.
+ *   - Every call returns APRIL_OK (0), APRIL_PENDING (1) or a negative error
+ *     code; april_last_error() gives a message for the calling thread.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ */
+#ifndef APRIL_H
+#define APRIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define APRIL_OK 0
+#define APRIL_PENDING 1
+#define APRIL_E_INVALID -1   /* bad argument, bad polygon, pair index out of range */
+#define APRIL_E_GRID -2      /* grid not exact, polygon outside the guarded grid,
+                                lists from different grids */
+#define APRIL_E_NOMEM -3     /* host or device allocation failed / over budget */
+#define APRIL_E_HIP -4       /* a HIP runtime call failed */
+#define APRIL_E_CORRUPT -5   /* lists not sorted/disjoint (validation) */
+#define APRIL_E_NODEV -6     /* no usable gfx950 device */
+
+/* verdicts (Sec. 4.2) */
+#define APRIL_TN 0
+#define APRIL_TH 1
+#define APRIL_INDECISIVE 2
+#define APRIL_BAD_PAIR 255   /* pair index out of range; not counted */
+
+/* ----------------------------------------------------------------- grid */
+/*
+ * The global 2^order x 2^order grid over the square data space
+ * [x0, x0 + side] x [y0, y0 + side] (Sec. 3.1).  order <= 16 so that
+ * Hilbert positions fit in uint32 (Sec. 3.2, "Practical considerations").
+ * side * 2^30 must be divisible by 2^order; x0, y0 must be lattice points.
+ * Polygons must keep clear of the outermost ring of cells (every vertex
+ * strictly between x0 + w and x0 + side - w, likewise in y), so the last
+ * Hilbert cell is never used and every interval end fits in uint32.
+ */
+typedef struct {
+    double x0, y0, side;
+    uint32_t order;
+    uint32_t flags;   /* reserved, must be 0 */
+} april_grid_t;
+
+/* ---------------------------------------------------------------- lists */
+/* A- and F-lists of one collection, resident on the host or on a device. */
+typedef struct april_lists april_lists_t;
+
+typedef struct {
+    uint64_t n_objects;
+    uint64_t n_a;          /* total A intervals */
+    uint64_t n_f;          /* total F intervals */
+    uint64_t device_bytes; /* bytes held in HBM (0 for host lists) */
+    int32_t on_device;     /* device ordinal, or -1 for host lists */
+    uint32_t codec;        /* APRIL_CODEC_* of the device copy */
+} april_lists_info_t;
+
+#define APRIL_STRICT 1u    /* april_build_lists: reject non-lattice coordinates
+                              instead of rounding them to the lattice */
+
+/*
+ * Build the A- and F-lists of n_polys simple polygons (Sec. 4.1; built by
+ * one-step intervalization, Sec. 6.2, Alg. 3).
+ *   xy       interleaved float64 vertices (x, y), counter-clockwise or not,
+ *            no closing duplicate; polygon k owns xy[2*vtx_off[k] .. 2*vtx_off[k+1])
+ *   vtx_off  n_polys + 1 offsets; every polygon needs >= 3 vertices
+ *   flags    0 or APRIL_STRICT
+ *   out      receives host-resident lists; free with april_lists_free
+ * Runs on the host, multi-threaded.  Errors: APRIL_E_INVALID (n_polys == 0,
+ * < 3 vertices, non-lattice coordinate under APRIL_STRICT), APRIL_E_GRID
+ * (a vertex in the outer cell ring or outside the grid), APRIL_E_NOMEM.
+ */
+int april_build_lists(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
+                      uint64_t n_polys, uint32_t flags, april_lists_t **out);
+
+/*
+ * Wrap caller-made lists (host arrays, copied) as host lists on `grid`.
+ * off_a/off_f: n_objects + 1 offsets; start/end: SoA uint32 endpoints.
+ * With validate != 0 every list must be sorted, disjoint and non-empty per
+ * interval (start < end <= next start) or APRIL_E_CORRUPT is returned.
+ */
+int april_lists_from_arrays(const april_grid_t *grid, uint64_t n_objects,
+                            const uint64_t *off_a, const uint32_t *start_a, const uint32_t *end_a,
+                            const uint64_t *off_f, const uint32_t *start_f, const uint32_t *end_f,
+                            int validate, april_lists_t **out);
+
+int april_lists_info(const april_lists_t *lists, april_lists_info_t *info);
+
+/* Copy host lists out (arrays sized from april_lists_info). */
+int april_lists_export(const april_lists_t *lists, uint64_t *off_a, uint32_t *start_a,
+                       uint32_t *end_a, uint64_t *off_f, uint32_t *start_f, uint32_t *end_f);
+
+#define APRIL_CODEC_RAW 0u   /* SoA uint32 start[] / end[] + uint64 CSR offsets */
+
+/*
+ * Upload host lists to the current HIP device in the layout the kernels
+ * read (Sec. 4.1: per object a sorted interval sequence; here split into
+ * SoA start[] and end[] arrays plus CSR offsets).  Allocates device memory
+ * owned by *out; asynchronous on hip_stream (the host lists must stay alive
+ * until the stream has passed the copy).  Free with april_lists_free.
+ */
+int april_lists_to_device(const april_lists_t *host, uint32_t codec, void *hip_stream,
+                          april_lists_t **out);
+
+void april_lists_free(april_lists_t *lists);
+
+/* ---------------------------------------------------------------- filter */
+#define APRIL_SCHED_PLAIN 0u    /* one wavefront per candidate pair */
+#define APRIL_SCHED_BATCHED 1u  /* length-binned persistent schedule */
+
+#define APRIL_VALIDATE 1u       /* check indices first; synchronous; APRIL_E_INVALID */
+
+typedef struct {
+    uint32_t schedule;   /* APRIL_SCHED_* */
+    uint32_t flags;      /* APRIL_VALIDATE */
+    uint32_t waves;      /* plain: resident wavefronts (0 = library default) */
+    uint32_t reserved;
+} april_filter_opts_t;
+
+/*
+ * The intermediate filter (Sec. 4.2, Alg. 2) on n_pairs candidate pairs.
+ *   R, S        device-resident lists on the same grid (else APRIL_E_GRID)
+ *   d_r, d_s    device uint32[n_pairs]: pair p is (R object d_r[p], S object d_s[p])
+ *   d_verdict   device uint8[n_pairs]: APRIL_TN / APRIL_TH / APRIL_INDECISIVE,
+ *               APRIL_BAD_PAIR for an out-of-range index
+ *   d_counts    device uint64[3] (TN, TH, INDECISIVE totals) or NULL;
+ *               overwritten, not accumulated
+ *   opts        NULL = plain schedule, library defaults
+ * Asynchronous on hip_stream; inputs are borrowed until the stream passes
+ * the call.  Every verdict is a pure function of the pair's four lists, so
+ * pair order and duplicates do not matter.  With APRIL_VALIDATE the call
+ * synchronizes and returns APRIL_E_INVALID if any index is out of range.
+ */
+int april_filter_pairs(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                       const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
+                       uint64_t *d_counts, const april_filter_opts_t *opts, void *hip_stream);
+
+/*
+ * Data movement of Alg. 2 itself, per pair: the bytes the sequential
+ * AA -> AF -> FA merge-joins with early exit must read and write.
+ * d_bytes[p] (device uint64[n_pairs]) = 8 (the pair's two uint32 ids)
+ *   + 16 per list whose CSR bounds Alg. 2 reads (two uint64 offsets)
+ *   + 8 per distinct interval it reads (two uint32 endpoints)
+ *   + 1 (the verdict); 0 for an out-of-range pair.
+ * Summed over a batch this is the "algorithmic bytes" of the filter.
+ * Computed on the device, one lane per pair; asynchronous on hip_stream.
+ */
+int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                     const uint32_t *d_s, uint64_t n_pairs, uint64_t *d_bytes, void *hip_stream);
+
+/* -------------------------------------------------------------- mbr join */
+/*
+ * Candidate pairs of the MBR filter step (Sec. 2): every (r, s) whose closed
+ * bounding rectangles intersect.  Boxes are host float64 [n][4] =
+ * (xmin, ymin, xmax, ymax).  Pairs are written sorted by (r, s) to the host
+ * arrays r_out, s_out of `capacity` entries; *n_out receives the count.  If
+ * capacity is too small nothing is written, *n_out holds the required count
+ * and APRIL_E_NOMEM is returned.  Host, multi-threaded.
+ */
+int april_mbr_join(const double *boxes_r, uint64_t n_r, const double *boxes_s, uint64_t n_s,
+                   uint32_t *r_out, uint32_t *s_out, uint64_t capacity, uint64_t *n_out);
+
+/* ---------------------------------------------------------------- misc */
+typedef struct {
+    int32_t device;
+    int32_t compute_units;
+    int32_t wavefront_size;
+    int32_t reserved;
+    uint64_t hbm_bytes;
+    char arch[64];
+    char name[128];
+} april_device_info_t;
+
+int april_device_info(april_device_info_t *info);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *april_last_error(void);
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
+#endif
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APRIL_H */

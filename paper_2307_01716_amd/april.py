@@ -1,0 +1,250 @@
+"""ctypes binding of libapril.so (include/april.h), same names as the C ABI.
+
+Argument marshalling only: every step of the filter runs in the library's
+HIP kernels.  Device arrays are torch tensors on a HIP device (their
+data_ptr() is passed through); streams are torch.cuda streams.  The binding
+raises if the library has not been built -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapril.so")
+
+OK, PENDING = 0, 1
+E_INVALID, E_GRID, E_NOMEM, E_HIP, E_CORRUPT, E_NODEV = -1, -2, -3, -4, -5, -6
+TN, TH, INDECISIVE, BAD_PAIR = 0, 1, 2, 255
+STRICT = 1
+CODEC_RAW = 0
+SCHED_PLAIN, SCHED_BATCHED = 0, 1
+VALIDATE = 1
+
+_ERRNAMES = {E_INVALID: "APRIL_E_INVALID", E_GRID: "APRIL_E_GRID", E_NOMEM: "APRIL_E_NOMEM",
+             E_HIP: "APRIL_E_HIP", E_CORRUPT: "APRIL_E_CORRUPT", E_NODEV: "APRIL_E_NODEV"}
+
+
+class AprilError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class april_grid_t(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("side", C.c_double),
+                ("order", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class april_lists_info_t(C.Structure):
+    _fields_ = [("n_objects", C.c_uint64), ("n_a", C.c_uint64), ("n_f", C.c_uint64),
+                ("device_bytes", C.c_uint64), ("on_device", C.c_int32), ("codec", C.c_uint32)]
+
+
+class april_filter_opts_t(C.Structure):
+    _fields_ = [("schedule", C.c_uint32), ("flags", C.c_uint32), ("waves", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class april_device_info_t(C.Structure):
+    _fields_ = [("device", C.c_int32), ("compute_units", C.c_int32),
+                ("wavefront_size", C.c_int32), ("reserved", C.c_int32),
+                ("hbm_bytes", C.c_uint64), ("arch", C.c_char * 64), ("name", C.c_char * 128)]
+
+
+_lib = None
+_exiting = False
+
+
+@atexit.register
+def _mark_exit():
+    global _exiting
+    _exiting = True
+
+
+def lib():
+    """Load libapril.so; raise (never fall back) when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "or python paper_2307_01716_amd/_build.py")
+    L = C.CDLL(LIB_PATH)
+    P, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
+    L.april_build_lists.argtypes = [C.POINTER(april_grid_t), P, P, u64, u32, C.POINTER(P)]
+    L.april_lists_from_arrays.argtypes = [C.POINTER(april_grid_t), u64, P, P, P, P, P, P, i32,
+                                          C.POINTER(P)]
+    L.april_lists_info.argtypes = [P, C.POINTER(april_lists_info_t)]
+    L.april_lists_export.argtypes = [P] * 7
+    L.april_lists_to_device.argtypes = [P, u32, P, C.POINTER(P)]
+    L.april_lists_free.argtypes = [P]
+    L.april_lists_free.restype = None
+    L.april_filter_pairs.argtypes = [P, P, P, P, u64, P, P, C.POINTER(april_filter_opts_t), P]
+    L.april_alg2_bytes.argtypes = [P, P, P, P, u64, P, P]
+    L.april_mbr_join.argtypes = [P, u64, P, u64, P, P, u64, C.POINTER(u64)]
+    L.april_device_info.argtypes = [C.POINTER(april_device_info_t)]
+    L.april_last_error.restype = C.c_char_p
+    for name in ("april_build_lists", "april_lists_from_arrays", "april_lists_info",
+                 "april_lists_export", "april_lists_to_device", "april_filter_pairs",
+                 "april_alg2_bytes",
+                 "april_mbr_join", "april_device_info"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def april_last_error() -> str:
+    return lib().april_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise AprilError(rc, april_last_error())
+    return rc
+
+
+def _np(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _grid(grid) -> april_grid_t:
+    x0, y0, side, order = grid.as_tuple() if hasattr(grid, "as_tuple") else grid
+    return april_grid_t(float(x0), float(y0), float(side), int(order), 0)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int address, or None)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("device array expected (a torch tensor on a HIP device)")
+    if not t.is_contiguous():
+        raise ValueError("device array must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Lists:
+    """Owning handle of an april_lists_t (host- or device-resident)."""
+
+    def __init__(self, handle: int, keep=None):
+        self._h = handle
+        self._keep = keep      # host lists a pending upload still reads
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("lists were freed")
+        return self._h
+
+    def info(self) -> april_lists_info_t:
+        inf = april_lists_info_t()
+        _check(lib().april_lists_info(self.handle, C.byref(inf)))
+        return inf
+
+    def __len__(self):
+        return int(self.info().n_objects)
+
+    def export(self):
+        """(offA, sA, eA, offF, sF, eF) numpy arrays of host lists."""
+        inf = self.info()
+        n, na, nf = int(inf.n_objects), int(inf.n_a), int(inf.n_f)
+        out = (np.empty(n + 1, np.uint64), np.empty(na, np.uint32), np.empty(na, np.uint32),
+               np.empty(n + 1, np.uint64), np.empty(nf, np.uint32), np.empty(nf, np.uint32))
+        _check(lib().april_lists_export(self.handle, *[_np(a) for a in out]))
+        return out
+
+    def free(self):
+        if self._h and not _exiting:
+            lib().april_lists_free(self._h)
+        self._h = None
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def april_build_lists(grid, xy: np.ndarray, vtx_off: np.ndarray, flags: int = 0) -> Lists:
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    vo = np.ascontiguousarray(vtx_off, dtype=np.uint64)
+    g = _grid(grid)
+    h = C.c_void_p()
+    _check(lib().april_build_lists(C.byref(g), _np(xy), _np(vo), len(vo) - 1, flags, C.byref(h)))
+    return Lists(h.value)
+
+
+def april_lists_from_arrays(grid, offA, sA, eA, offF, sF, eF, validate: bool = True) -> Lists:
+    arrs = [np.ascontiguousarray(offA, np.uint64), np.ascontiguousarray(sA, np.uint32),
+            np.ascontiguousarray(eA, np.uint32), np.ascontiguousarray(offF, np.uint64),
+            np.ascontiguousarray(sF, np.uint32), np.ascontiguousarray(eF, np.uint32)]
+    g = _grid(grid)
+    h = C.c_void_p()
+    _check(lib().april_lists_from_arrays(C.byref(g), len(arrs[0]) - 1, *[_np(a) for a in arrs],
+                                         int(validate), C.byref(h)))
+    return Lists(h.value)
+
+
+def april_lists_to_device(host: Lists, codec: int = CODEC_RAW, stream=None) -> Lists:
+    h = C.c_void_p()
+    _check(lib().april_lists_to_device(host.handle, codec, _stream(stream), C.byref(h)))
+    return Lists(h.value, keep=host)
+
+
+def april_filter_pairs(R: Lists, S: Lists, r, s, verdict, counts=None, schedule=SCHED_PLAIN,
+                       flags=0, waves=0, stream=None) -> int:
+    """r, s: int32/uint32 device tensors [P]; verdict: uint8 device tensor [P];
+    counts: int64 device tensor [3] or None."""
+    n = int(r.numel()) if hasattr(r, "numel") else (0 if isinstance(r, int) else int(len(r)))
+    opts = april_filter_opts_t(schedule, flags, waves, 0)
+    return _check(lib().april_filter_pairs(R.handle, S.handle, _dptr(r), _dptr(s), n,
+                                           _dptr(verdict), _dptr(counts), C.byref(opts),
+                                           _stream(stream)))
+
+
+def april_alg2_bytes(R: Lists, S: Lists, r, s, bytes_out, stream=None) -> int:
+    """Per-pair bytes Alg. 2 moves (device uint64 tensor [P], here int64)."""
+    n = int(r.numel())
+    return _check(lib().april_alg2_bytes(R.handle, S.handle, _dptr(r), _dptr(s), n,
+                                         _dptr(bytes_out), _stream(stream)))
+
+
+def april_mbr_join(boxes_r: np.ndarray, boxes_s: np.ndarray):
+    """Candidate pairs (r, s) of intersecting closed MBRs, sorted by (r, s)."""
+    br = np.ascontiguousarray(boxes_r, np.float64)
+    bs = np.ascontiguousarray(boxes_s, np.float64)
+    need = C.c_uint64()
+    L = lib()
+    rc = L.april_mbr_join(_np(br), len(br), _np(bs), len(bs), None, None, 0, C.byref(need))
+    if rc != E_NOMEM:
+        _check(rc)
+    r = np.empty(need.value, np.uint32)
+    s = np.empty(need.value, np.uint32)
+    _check(L.april_mbr_join(_np(br), len(br), _np(bs), len(bs), _np(r), _np(s), need.value,
+                            C.byref(need)))
+    return r, s
+
+
+def april_device_info() -> dict:
+    inf = april_device_info_t()
+    _check(lib().april_device_info(C.byref(inf)))
+    return {"device": inf.device, "compute_units": inf.compute_units,
+            "wavefront_size": inf.wavefront_size, "hbm_bytes": inf.hbm_bytes,
+            "arch": inf.arch.decode(), "name": inf.name.decode()}

@@ -1,0 +1,330 @@
+// The APRIL intermediate filter on gfx950 (Sec. 4.2, Alg. 2).
+//
+// Plain schedule: one wavefront per candidate pair.  The wave reads the
+// pair's ids and the CSR bounds of its four lists, then runs the three
+// interval joins of Alg. 2 in order (AA; then AF; then FA) with early exit.
+//
+// A join of sorted, disjoint lists X and Y is done wave-cooperatively as a
+// merge path.  Alg. 2's merge loop visits states (i, j); the state after t
+// steps is the point of the merge path on diagonal i + j = t, where the
+// merged order takes X_i before Y_j iff X_i.end <= Y_j.end (Alg. 2 advances
+// i on ties).  A tile of 64*K consecutive diagonals is processed at once:
+// both lists' next 64*K intervals are staged in LDS, lane l binary-searches
+// its start state on diagonal l*K, then runs K steps of Alg. 2's loop from
+// there.  The lanes together perform exactly the comparisons of Alg. 2 over
+// the tile, so "some lane saw an overlap" equals "Alg. 2 returns true within
+// these steps"; a ballot decides, and the state on the tile's last diagonal
+// (lane 63's end state) starts the next tile.  The join ends as soon as one
+// list is exhausted, like Alg. 2.
+//
+// Interval lists are SoA uint32 start[] / end[] arrays in HBM with uint64
+// CSR offsets per object; tile loads are coalesced 4-byte loads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace april {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+struct ListView {
+    const uint64_t *off;
+    const uint32_t *s;
+    const uint32_t *e;
+};
+
+struct FilterArgs {
+    ListView Ar, Fr, As, Fs;
+    const uint32_t *r;
+    const uint32_t *s;
+    uint64_t n_pairs;
+    uint64_t n_r, n_s;
+    uint8_t *verdict;
+    unsigned long long *counts;
+};
+
+// Make this wave's LDS writes visible to its own later LDS reads (and keep
+// the compiler from moving LDS accesses across this point).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Any overlap between X = [xs, xe)[0..n) and Y = [ys, ye)[0..m)?  Result is
+// the one Alg. 2's IntervalJoin returns.  lx, ly: this wave's LDS tiles of
+// 64*K entries each.
+template <int K>
+__device__ bool wave_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
+                          uint32_t n, const uint32_t *__restrict__ ys,
+                          const uint32_t *__restrict__ ye, uint32_t m, uint2 *lx, uint2 *ly,
+                          uint32_t lane) {
+    constexpr uint32_t T = kWave * K;
+    uint32_t i0 = 0, j0 = 0;
+    while (i0 < n && j0 < m) {
+        const uint32_t nx = min(T, n - i0), ny = min(T, m - j0);
+        // all of this wave's reads of the previous tile are done before the
+        // tile is overwritten
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const uint32_t t = lane + k * kWave;
+            if (t < nx) lx[t] = make_uint2(xs[i0 + t], xe[i0 + t]);
+            if (t < ny) ly[t] = make_uint2(ys[j0 + t], ye[j0 + t]);
+        }
+        wave_lds_sync();
+        // start state of this lane: merge-path point on diagonal d
+        const uint32_t d = lane * K;
+        uint32_t lo = d > ny ? d - ny : 0, hi = min(d, nx);
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (lx[mid].y <= ly[d - 1 - mid].y) lo = mid + 1;
+            else hi = mid;
+        }
+        uint32_t i = lo, j = d - lo;   // i > nx only past the end of both lists
+        bool found = false;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (!found && i < nx && j < ny) {
+                const uint2 x = lx[i], y = ly[j];
+                if (x.x < y.y && y.x < x.y) found = true;
+                else if (x.y <= y.y) i++;
+                else j++;
+            }
+        }
+        if (__any(found)) return true;
+        i0 += uniform(__shfl(i, kWave - 1));
+        j0 += uniform(__shfl(j, kWave - 1));
+    }
+    return false;
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_filter_plain(FilterArgs a) {
+    __shared__ uint2 lds[kWavesPerBlock][2][kWave * K];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t w = uniform(threadIdx.x / kWave);
+    uint2 *lx = lds[w][0], *ly = lds[w][1];
+    const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+    unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
+    for (uint64_t p = uint64_t(blockIdx.x) * kWavesPerBlock + w; p < a.n_pairs; p += n_waves) {
+        const uint32_t r = uniform(a.r[p]), s = uniform(a.s[p]);
+        uint8_t v;
+        if (r >= a.n_r || s >= a.n_s) {
+            v = APRIL_BAD_PAIR;
+        } else {
+            const uint64_t ar0 = a.Ar.off[r], ar1 = a.Ar.off[r + 1];
+            const uint64_t as0 = a.As.off[s], as1 = a.As.off[s + 1];
+            const uint64_t fr0 = a.Fr.off[r], fr1 = a.Fr.off[r + 1];
+            const uint64_t fs0 = a.Fs.off[s], fs1 = a.Fs.off[s + 1];
+            const uint32_t nar = uint32_t(ar1 - ar0), nas = uint32_t(as1 - as0);
+            const uint32_t nfr = uint32_t(fr1 - fr0), nfs = uint32_t(fs1 - fs0);
+            if (!wave_join<K>(a.Ar.s + ar0, a.Ar.e + ar0, nar, a.As.s + as0, a.As.e + as0, nas,
+                              lx, ly, lane)) {
+                v = APRIL_TN;
+            } else if (wave_join<K>(a.Ar.s + ar0, a.Ar.e + ar0, nar, a.Fs.s + fs0, a.Fs.e + fs0,
+                                    nfs, lx, ly, lane) ||
+                       wave_join<K>(a.Fr.s + fr0, a.Fr.e + fr0, nfr, a.As.s + as0, a.As.e + as0,
+                                    nas, lx, ly, lane)) {
+                v = APRIL_TH;
+            } else {
+                v = APRIL_INDECISIVE;
+            }
+        }
+        if (lane == 0) a.verdict[p] = v;
+        c_tn += (v == APRIL_TN);
+        c_th += (v == APRIL_TH);
+        c_ind += (v == APRIL_INDECISIVE);
+    }
+    if (a.counts && lane == 0) {
+        if (c_tn) atomicAdd(&a.counts[0], c_tn);
+        if (c_th) atomicAdd(&a.counts[1], c_th);
+        if (c_ind) atomicAdd(&a.counts[2], c_ind);
+    }
+}
+
+// Alg. 2's IntervalJoin run sequentially by one lane; *rx, *ry receive how
+// many leading elements of X and Y the loop read.
+__device__ bool seq_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
+                         uint32_t n, const uint32_t *__restrict__ ys,
+                         const uint32_t *__restrict__ ye, uint32_t m, uint32_t *rx, uint32_t *ry) {
+    uint32_t i = 0, j = 0, ri = 0, rj = 0;
+    bool found = false;
+    while (i < n && j < m) {
+        ri = i + 1;
+        rj = j + 1;
+        const uint32_t a = xs[i], b = xe[i], c = ys[j], d = ye[j];
+        if (a < d && c < b) { found = true; break; }
+        if (b <= d) i++;
+        else j++;
+    }
+    *rx = ri;
+    *ry = rj;
+    return found;
+}
+
+// One lane per pair: the verdict of Alg. 2 and the bytes it moves --
+// 8 for the pair's ids, 16 per list whose CSR bounds it reads, 8 per distinct
+// interval it reads (two uint32 endpoints), 1 for the verdict.
+__global__ void k_alg2_bytes(FilterArgs a, unsigned long long *bytes) {
+    for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < a.n_pairs;
+         p += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t r = a.r[p], s = a.s[p];
+        if (r >= a.n_r || s >= a.n_s) { bytes[p] = 0; continue; }
+        const uint64_t ar0 = a.Ar.off[r], nar = a.Ar.off[r + 1] - ar0;
+        const uint64_t as0 = a.As.off[s], nas = a.As.off[s + 1] - as0;
+        uint32_t x, y, ax_r, ax_s, nfs = 0, nfr = 0, lists = 2;
+        if (seq_join(a.Ar.s + ar0, a.Ar.e + ar0, uint32_t(nar), a.As.s + as0, a.As.e + as0,
+                     uint32_t(nas), &x, &y)) {
+            ax_r = x;
+            ax_s = y;
+            const uint64_t fs0 = a.Fs.off[s], nf = a.Fs.off[s + 1] - fs0;
+            lists++;
+            const bool af = seq_join(a.Ar.s + ar0, a.Ar.e + ar0, uint32_t(nar), a.Fs.s + fs0,
+                                     a.Fs.e + fs0, uint32_t(nf), &x, &y);
+            ax_r = max(ax_r, x);
+            nfs = y;
+            if (!af) {
+                const uint64_t fr0 = a.Fr.off[r], nfr_ = a.Fr.off[r + 1] - fr0;
+                lists++;
+                seq_join(a.Fr.s + fr0, a.Fr.e + fr0, uint32_t(nfr_), a.As.s + as0, a.As.e + as0,
+                         uint32_t(nas), &x, &y);
+                nfr = x;
+                ax_s = max(ax_s, y);
+            }
+        } else {
+            ax_r = x;
+            ax_s = y;
+        }
+        bytes[p] = 8ull + 16ull * lists + 8ull * (uint64_t(ax_r) + ax_s + nfs + nfr) + 1ull;
+    }
+}
+
+__global__ void k_zero_counts(unsigned long long *c) {
+    if (threadIdx.x < 3) c[threadIdx.x] = 0;
+}
+
+__global__ void k_check_pairs(const uint32_t *r, const uint32_t *s, uint64_t n, uint64_t n_r,
+                              uint64_t n_s, unsigned int *bad) {
+    for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
+         p += uint64_t(gridDim.x) * blockDim.x)
+        if (r[p] >= n_r || s[p] >= n_s) atomicOr(bad, 1u);
+}
+
+struct DeviceState {
+    int cus = 0;
+    unsigned int *flag = nullptr;   // one word for index validation
+};
+
+int device_state(DeviceState **out) {
+    static DeviceState states[64];
+    int dev = 0;
+    APRIL_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(APRIL_E_NODEV, "device ordinal out of range");
+    DeviceState &st = states[dev];
+    if (!st.cus) {
+        hipDeviceProp_t p;
+        APRIL_HIP_TRY(hipGetDeviceProperties(&p, dev));
+        if (std::string(p.gcnArchName).rfind("gfx950", 0) != 0)
+            return fail(APRIL_E_NODEV, std::string("library built for gfx950, device is ") + p.gcnArchName);
+        APRIL_HIP_TRY(hipMalloc(&st.flag, sizeof(unsigned int)));
+        st.cus = p.multiProcessorCount;
+    }
+    *out = &st;
+    return APRIL_OK;
+}
+
+}  // namespace
+}  // namespace april
+
+using namespace april;
+
+static int check_lists(const april_lists_t *R, const april_lists_t *S) {
+    if (!R || !S) return fail(APRIL_E_INVALID, "NULL lists");
+    if (R->device < 0 || S->device < 0) return fail(APRIL_E_INVALID, "lists must be on a device");
+    if (R->device != S->device) return fail(APRIL_E_INVALID, "lists on different devices");
+    if (!same_grid(R->grid, S->grid)) return fail(APRIL_E_GRID, "R and S lists use different grids");
+    int cur = 0;
+    APRIL_HIP_TRY(hipGetDevice(&cur));
+    if (cur != R->device) return fail(APRIL_E_INVALID, "current device does not hold the lists");
+    return APRIL_OK;
+}
+
+static FilterArgs make_args(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                            const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
+                            unsigned long long *counts) {
+    FilterArgs a;
+    a.Ar = {R->d.off_a, R->d.start_a, R->d.end_a};
+    a.Fr = {R->d.off_f, R->d.start_f, R->d.end_f};
+    a.As = {S->d.off_a, S->d.start_a, S->d.end_a};
+    a.Fs = {S->d.off_f, S->d.start_f, S->d.end_f};
+    a.r = d_r;
+    a.s = d_s;
+    a.n_pairs = n_pairs;
+    a.n_r = R->n;
+    a.n_s = S->n;
+    a.verdict = d_verdict;
+    a.counts = counts;
+    return a;
+}
+
+extern "C" int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                                const uint32_t *d_s, uint64_t n_pairs, uint64_t *d_bytes,
+                                void *hip_stream) {
+    clear_error();
+    if (int rc = check_lists(R, S)) return rc;
+    if (n_pairs == 0) return APRIL_OK;
+    if (!d_r || !d_s || !d_bytes) return fail(APRIL_E_INVALID, "NULL pair/bytes array");
+    DeviceState *st;
+    if (int rc = device_state(&st)) return rc;
+    FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, nullptr, nullptr);
+    const uint64_t blocks = std::min<uint64_t>((n_pairs + 255) / 256, uint64_t(st->cus) * 16);
+    k_alg2_bytes<<<dim3(uint32_t(blocks)), dim3(256), 0, static_cast<hipStream_t>(hip_stream)>>>(
+        a, reinterpret_cast<unsigned long long *>(d_bytes));
+    APRIL_HIP_TRY(hipGetLastError());
+    return APRIL_OK;
+}
+
+extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                                  const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
+                                  uint64_t *d_counts, const april_filter_opts_t *opts,
+                                  void *hip_stream) {
+    clear_error();
+    if (int rc = check_lists(R, S)) return rc;
+    if (n_pairs && (!d_r || !d_s || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
+    april_filter_opts_t o{};
+    if (opts) o = *opts;
+    if (o.schedule != APRIL_SCHED_PLAIN) return fail(APRIL_E_INVALID, "unknown schedule");
+    DeviceState *st;
+    if (int rc = device_state(&st)) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    auto *counts = reinterpret_cast<unsigned long long *>(d_counts);
+    if (counts) {
+        k_zero_counts<<<1, 64, 0, stream>>>(counts);
+        APRIL_HIP_TRY(hipGetLastError());
+    }
+    if (n_pairs == 0) return APRIL_OK;
+    if (o.flags & APRIL_VALIDATE) {
+        APRIL_HIP_TRY(hipMemsetAsync(st->flag, 0, sizeof(unsigned int), stream));
+        k_check_pairs<<<1024, 256, 0, stream>>>(d_r, d_s, n_pairs, R->n, S->n, st->flag);
+        APRIL_HIP_TRY(hipGetLastError());
+        unsigned int bad = 0;
+        APRIL_HIP_TRY(hipMemcpyAsync(&bad, st->flag, sizeof(bad), hipMemcpyDeviceToHost, stream));
+        APRIL_HIP_TRY(hipStreamSynchronize(stream));
+        if (bad) return fail(APRIL_E_INVALID, "pair index out of range");
+    }
+    FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, d_verdict, counts);
+    uint64_t waves = o.waves ? o.waves : uint64_t(st->cus) * 32;
+    waves = std::min<uint64_t>(waves, n_pairs);
+    const uint64_t blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    k_filter_plain<4><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a);
+    APRIL_HIP_TRY(hipGetLastError());
+    return APRIL_OK;
+}

@@ -1,0 +1,235 @@
+"""Parity of the HIP filter with the oracle (bit-exact verdicts and counts).
+
+Cases:
+  * random interval lists with no geometry behind them: lengths 0 .. 10^5
+    around the kernel's tile edges, dense and sparse overlap, lists that
+    touch everywhere without overlapping (full scans ending in a true
+    negative) and the same with one overlap planted near the end;
+  * the tiny workload end to end (the library's own lists vs the oracle's,
+    verdicts, counts, Alg. 2 byte counts);
+  * the at-scale workload (200k x 200k polygons, ~4.7M pairs) in the launch
+    configuration the benchmark times: every verdict checked against
+    properties that hold at any size, a random sample checked against the
+    oracle one by one;
+  * edge cases: no pairs, out-of-range indices, duplicated pairs.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.intervals import ListSet, complement_list, random_lists
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2307_01716_amd import april  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cuda(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).cuda()
+
+
+def device_lists(grid, lists: oracle.Lists):
+    h = april.april_lists_from_arrays(grid, lists.offA, lists.sA, lists.eA, lists.offF, lists.sF,
+                                      lists.eF, validate=True)
+    d = april.april_lists_to_device(h)
+    torch.cuda.synchronize()
+    return d
+
+
+def gpu_filter(LRd, LSd, r, s, **kw):
+    P = len(r)
+    v = torch.full((max(P, 1),), 77, dtype=torch.uint8, device="cuda")[:P]
+    c = torch.full((3,), -1, dtype=torch.int64, device="cuda")
+    april.april_filter_pairs(LRd, LSd, cuda(r), cuda(s), v, c, **kw)
+    torch.cuda.synchronize()
+    return v.cpu().numpy(), c.cpu().numpy()
+
+
+GRID = (0.0, 0.0, float(1 << 16) * 2.0 ** -30 * (1 << 16), 16)
+
+
+def _random_collection(rng, n, kind):
+    A, F = [], []
+    for k in range(n):
+        if kind == "edges":
+            L = int(rng.choice([0, 1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513,
+                                1000, 4095, 4097]))
+        elif kind == "long":
+            L = int(rng.choice([1, 3, 10_000, 65_536, 100_000]))
+        else:
+            L = int(rng.integers(0, 300))
+        lo = int(rng.integers(0, 1 << 20))
+        span = max(4 * L + 8, int(rng.integers(2 * L + 2, 64 * L + 64)))
+        a = random_lists(rng, max(L, 1), lo, lo + span)
+        f = random_lists(rng, int(rng.integers(0, max(L // 2, 1) + 1)), lo, lo + span)
+        A.append(a)
+        F.append(f)
+    a = ListSet.from_lists(A)
+    f = ListSet.from_lists(F)
+    return oracle.Lists(a.off, a.start, a.end, f.off, f.start, f.end)
+
+
+@pytest.mark.parametrize("kind,n,P", [("mixed", 400, 20_000), ("edges", 300, 20_000),
+                                      ("long", 12, 150)])
+def test_random_lists(kind, n, P):
+    rng = np.random.default_rng({"mixed": 1, "edges": 2, "long": 3}[kind])
+    say(f"[random lists] kind={kind} n={n} P={P}")
+    LR = _random_collection(rng, n, kind)
+    LS = _random_collection(rng, n, kind)
+    r = rng.integers(0, n, P).astype(np.uint32)
+    s = rng.integers(0, n, P).astype(np.uint32)
+    want = oracle.filter_pairs(LR, LS, r, s)
+    got, cnt = gpu_filter(device_lists(GRID, LR), device_lists(GRID, LS), r, s)
+    assert np.array_equal(got, want)
+    assert np.array_equal(cnt, np.bincount(want, minlength=3))
+
+
+@pytest.mark.parametrize("k", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 30_000, 300_000])
+def test_touching_lists(k):
+    """X against its gaps: no overlap anywhere (a full merge), then the same
+    with one gap widened by one cell at a random place (one overlap)."""
+    rng = np.random.default_rng(k)
+    say(f"[touching] k={k}")
+    X = random_lists(rng, k + 1, 0, 8 * k + 64)
+    C = complement_list(*X)
+    C2 = (C[0].copy(), C[1].copy())
+    C3 = (C[0].copy(), C[1].copy())
+    if k >= 1:
+        C2[1][-1] += 1            # overlap at the very end of the merge
+        t = int(rng.integers(0, k))
+        C3[0][t] -= 1             # overlap somewhere inside
+    z = (np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    # object 0: X with F = X; objects of S: gaps (A) with F = gaps
+    LR = ListSet.from_lists([X]), ListSet.from_lists([X])
+    LS = ListSet.from_lists([C, C2, C3, X]), ListSet.from_lists([z, C2, z, z])
+    LRo = oracle.Lists(LR[0].off, LR[0].start, LR[0].end, LR[1].off, LR[1].start, LR[1].end)
+    LSo = oracle.Lists(LS[0].off, LS[0].start, LS[0].end, LS[1].off, LS[1].start, LS[1].end)
+    r = np.zeros(4, np.uint32)
+    s = np.arange(4, dtype=np.uint32)
+    want = oracle.filter_pairs(LRo, LSo, r, s)
+    assert want[0] == oracle.TN and want[1] == oracle.TH and want[3] == oracle.TH
+    got, cnt = gpu_filter(device_lists(GRID, LRo), device_lists(GRID, LSo), r, s)
+    assert np.array_equal(got, want)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    R, S, g = synth.configs.tiny()
+    LR = oracle.build_lists(g, R)
+    LS = oracle.build_lists(g, S)
+    r, s = oracle.mbr_join(R, S)
+    v, b = oracle.filter_pairs(LR, LS, r, s, want_bytes=True)
+    return R, S, g, LR, LS, r, s, v, b
+
+
+def test_tiny_end_to_end(tiny):
+    R, S, g, LR, LS, r, s, v, b = tiny
+    say(f"[tiny] pairs={len(r)}")
+    hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
+    hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
+    dR = april.april_lists_to_device(hR)
+    dS = april.april_lists_to_device(hS)
+    got, cnt = gpu_filter(dR, dS, r, s)
+    assert np.array_equal(got, v)
+    assert np.array_equal(cnt, np.bincount(v, minlength=3))
+    by = torch.zeros(len(r), dtype=torch.int64, device="cuda")
+    april.april_alg2_bytes(dR, dS, cuda(r), cuda(s), by)
+    torch.cuda.synchronize()
+    assert np.array_equal(by.cpu().numpy().astype(np.uint64), b)
+
+
+def test_tiny_waves_and_duplicates(tiny):
+    R, S, g, LR, LS, r, s, v, b = tiny
+    dR, dS = device_lists(g, LR), device_lists(g, LS)
+    rng = np.random.default_rng(9)
+    perm = rng.integers(0, len(r), 3 * len(r))          # shuffled, with repeats
+    for waves in (1, 7, 64, 100_000):
+        say(f"[tiny] waves={waves}")
+        got, cnt = gpu_filter(dR, dS, r[perm], s[perm], waves=waves)
+        assert np.array_equal(got, v[perm])
+        assert np.array_equal(cnt, np.bincount(v[perm], minlength=3))
+
+
+def test_empty_and_bad_pairs(tiny):
+    R, S, g, LR, LS, r, s, v, b = tiny
+    dR, dS = device_lists(g, LR), device_lists(g, LS)
+    say("[edge] no pairs")
+    got, cnt = gpu_filter(dR, dS, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert len(got) == 0 and np.array_equal(cnt, [0, 0, 0])
+    say("[edge] out-of-range indices")
+    rr = np.array([0, len(R), 5, 0xFFFFFFFF], np.uint32)
+    ss = np.array([0, 0, len(S) + 3, 1], np.uint32)
+    got, cnt = gpu_filter(dR, dS, rr, ss)
+    want0 = oracle.filter_pairs(LR, LS, rr[:1], ss[:1])[0]
+    assert got[0] == want0
+    assert list(got[1:]) == [april.BAD_PAIR] * 3
+    assert cnt.sum() == 1
+    with pytest.raises(april.AprilError) as e:
+        gpu_filter(dR, dS, rr, ss, flags=april.VALIDATE)
+    assert e.value.code == april.E_INVALID
+    got, cnt = gpu_filter(dR, dS, r[:50], s[:50], flags=april.VALIDATE)
+    assert np.array_equal(got, v[:50])
+
+
+def test_grid_mismatch(tiny):
+    R, S, g, LR, LS, r, s, v, b = tiny
+    dR = device_lists(g, LR)
+    other = synth.Grid(g.x0, g.y0, g.side * 2, g.order)
+    dS = device_lists(other, LS)
+    with pytest.raises(april.AprilError) as e:
+        gpu_filter(dR, dS, r[:4], s[:4])
+    assert e.value.code == april.E_GRID
+
+
+@pytest.fixture(scope="module")
+def scale():
+    say("[scale] generating 200k x 200k")
+    R, S, g = synth.configs.scale()
+    r, s = oracle.mbr_join(R, S)
+    hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
+    hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
+    dR = april.april_lists_to_device(hR)
+    dS = april.april_lists_to_device(hS)
+    torch.cuda.synchronize()
+    return R, S, g, r, s, dR, dS
+
+
+def test_scale_sampled_against_oracle(scale):
+    R, S, g, r, s, dR, dS = scale
+    say(f"[scale] plain filter over {len(r)} pairs")
+    got, cnt = gpu_filter(dR, dS, r, s)
+    assert np.array_equal(cnt, np.bincount(got, minlength=3))
+    assert cnt.sum() == len(r)
+    rng = np.random.default_rng(17)
+    pick = np.sort(rng.choice(len(r), 3000, replace=False))
+    ur, ir = np.unique(r[pick], return_inverse=True)
+    us, is_ = np.unique(s[pick], return_inverse=True)
+    say(f"[scale] oracle lists for {len(ur)} + {len(us)} sampled polygons")
+    LR = oracle.build_lists(g, R.subset(ur))
+    LS = oracle.build_lists(g, S.subset(us))
+    want = oracle.filter_pairs(LR, LS, ir.astype(np.uint32), is_.astype(np.uint32))
+    assert np.array_equal(got[pick], want)
+    assert set(np.unique(want)) == {0, 1, 2}
+
+
+def test_scale_swapped_roles(scale):
+    R, S, g, r, s, dR, dS = scale
+    say("[scale] swapped roles")
+    a, _ = gpu_filter(dR, dS, r, s)
+    b, _ = gpu_filter(dS, dR, s, r)
+    assert np.array_equal(a, b)

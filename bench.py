@@ -44,8 +44,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--schedule", choices=["plain"], default="plain")
-    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--schedule", choices=["both", "plain", "batched"], default="both")
+    ap.add_argument("--no-tune", action="store_true", help="batched: library defaults, no sweep")
+    ap.add_argument("--no-graph", action="store_true", help="batched: eager launches")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB three times (reference dispatches for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
@@ -129,55 +132,117 @@ def main():
     del by
     log(f"Alg. 2 bytes per launch: {alg_bytes / 1e9:.3f} GB ({alg_bytes / P:.0f} B/pair)")
 
-    sched = april.SCHED_PLAIN
+    def timed(fn, steps, warmup):
+        """W untimed calls, then K timed ones; per-call HIP event times (ms)
+        on the launch stream and the wall time of the K calls."""
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        return np.array([a.elapsed_time(b) for a, b in ev]), wall
 
-    def step():
-        april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=sched, waves=args.waves,
-                                 stream=stream)
+    def form(name, launch_ms, wall):
+        ms = wall * 1e3 / args.steps
+        c = counts.cpu().numpy()
+        assert int(c.sum()) == P, f"{name}: counts do not cover every pair"
+        d = {"ms_per_step": ms, "kernel_ms": float(launch_ms.mean()),
+             "kernel_ms_p10": float(np.percentile(launch_ms, 10)),
+             "kernel_ms_p90": float(np.percentile(launch_ms, 90)),
+             "pairs_per_s": P / (ms / 1e3),
+             "alg_GBps": alg_bytes / (launch_ms.mean() / 1e3) / 1e9,
+             "verdicts": {"TN": int(c[0]), "TH": int(c[1]), "IND": int(c[2])}}
+        log(f"{name}: {ms:.3f} ms/step, kernel {d['kernel_ms']:.3f} ms (p10 {d['kernel_ms_p10']:.3f} "
+            f"p90 {d['kernel_ms_p90']:.3f}); {d['pairs_per_s'] / 1e9:.3f} G pairs/s; "
+            f"{d['alg_GBps']:.0f} GB/s algorithmic; TN/TH/IND = {c.tolist()}")
+        return d
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        step()
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    ms_per_step = wall * 1e3 / args.steps
-    c = counts.cpu().numpy()
-    assert int(c.sum()) == P, "counts do not cover every pair"
-    value = P / (ms_per_step / 1e3)
-    achieved = alg_bytes / (launch_ms.mean() / 1e3) / 1e9
-    log(f"plain: {ms_per_step:.3f} ms/step, kernel {launch_ms.mean():.3f} ms "
-        f"(p10 {np.percentile(launch_ms, 10):.3f} p90 {np.percentile(launch_ms, 90):.3f}); "
-        f"{value / 1e9:.3f} G pairs/s; TN/TH/IND = {c.tolist()}")
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x 1 GiB device-to-device copies")
 
+    forms = {}
+    if args.schedule in ("both", "plain"):
+        def plain():
+            april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_PLAIN,
+                                     stream=stream)
+        forms["plain"] = form("plain", *timed(plain, args.steps, args.warmup))
+        plain_verdict = verdict.clone()
+
+    if args.schedule in ("both", "batched"):
+        from paper_2307_01716_amd import tune
+        ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
+        cfg = {}
+        if not args.no_tune:
+            t0 = time.time()
+            cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3)
+            log(f"autotune: {len(table)} settings in {time.time() - t0:.1f}s; best {cfg} "
+                f"({best_ms:.3f} ms)")
+
+        def batched_eager():
+            april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_BATCHED,
+                                     workspace=ws, stream=stream, **cfg)
+
+        if args.no_graph:
+            fn = batched_eager
+        else:
+            batched_eager()
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            cap = torch.cuda.Stream()
+            cap.wait_stream(stream)
+            with torch.cuda.stream(cap):
+                with torch.cuda.graph(graph, stream=cap):
+                    april.april_filter_pairs(dR, dS, r, s, verdict, counts,
+                                             schedule=april.SCHED_BATCHED, workspace=ws,
+                                             stream=torch.cuda.current_stream(), **cfg)
+            torch.cuda.synchronize()
+            fn = graph.replay
+        forms["batched"] = form("batched", *timed(fn, args.steps, args.warmup))
+        forms["batched"]["tuning"] = cfg
+        forms["batched"]["hipgraph"] = not args.no_graph
+        if "plain" in forms:
+            assert torch.equal(verdict, plain_verdict), "batched and plain verdicts differ"
+            forms["batched"]["speedup_vs_plain"] = (forms["plain"]["kernel_ms"] /
+                                                    forms["batched"]["kernel_ms"])
+            log(f"batched / plain speedup: {forms['batched']['speedup_vs_plain']:.2f}x")
+
+    main_form = "batched" if "batched" in forms else "plain"
+    f = forms[main_form]
     out = {
-        "metric": "candidate pairs filtered/s (plain, one wavefront per pair)",
-        "value": value,
+        "metric": "candidate pairs filtered/s (" + (
+            "batched persistent schedule, hipGraph replay" if main_form == "batched"
+            else "plain, one wavefront per pair") + ")",
+        "value": f["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": f["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "scale: 200k x 200k star polygons, grid 2^16, all MBR candidate pairs",
-                   "pairs": P, "schedule": "plain", "verdicts": {"TN": int(c[0]), "TH": int(c[1]),
-                                                                  "IND": int(c[2])}},
-        "kernel_ms": float(launch_ms.mean()),
-        "hbm_GBps_algorithmic": achieved,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                   "pairs": P, "schedule": main_form, "verdicts": f["verdicts"]},
+        "forms": forms,
+        "alg_bytes_per_launch": alg_bytes,
+        "roofline": {"bound": "hbm", "achieved": f["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": f["alg_GBps"] / HBM_PEAK_GBS, "traffic": None},
     }
     if not args.no_cpu_baseline:
         t0 = time.time()

@@ -108,8 +108,11 @@ int april_build_lists(const april_grid_t *grid, const double *xy, const uint64_t
 /*
  * Wrap caller-made lists (host arrays, copied) as host lists on `grid`.
  * off_a/off_f: n_objects + 1 offsets; start/end: SoA uint32 endpoints.
- * With validate != 0 every list must be sorted, disjoint and non-empty per
- * interval (start < end <= next start) or APRIL_E_CORRUPT is returned.
+ * Lists must be what APRIL lists are: sorted, disjoint, non-empty intervals
+ * (start < end <= next start), and every F interval inside one A interval
+ * (a Full cell is a cell of the object, Sec. 4.1).  The batched schedule
+ * relies on the last property.  With validate != 0 all of this is checked
+ * and APRIL_E_CORRUPT returned on a violation.
  */
 int april_lists_from_arrays(const april_grid_t *grid, uint64_t n_objects,
                             const uint64_t *off_a, const uint32_t *start_a, const uint32_t *end_a,
@@ -143,14 +146,45 @@ void april_lists_free(april_lists_t *lists);
 #define APRIL_VALIDATE 1u       /* check indices first; synchronous; APRIL_E_INVALID */
 
 typedef struct {
-    uint32_t schedule;   /* APRIL_SCHED_* */
-    uint32_t flags;      /* APRIL_VALIDATE */
-    uint32_t waves;      /* plain: resident wavefronts (0 = library default) */
-    uint32_t reserved;
+    uint32_t schedule;     /* APRIL_SCHED_* */
+    uint32_t flags;        /* APRIL_VALIDATE */
+    uint32_t waves;        /* resident wavefronts (0 = library default) */
+    uint32_t tile;         /* batched: intervals per list kept in LDS per wavefront:
+                              128, 256 or 512 (0 = 256) */
+    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2) */
+    uint32_t thread_max;   /* batched: pairs whose four lists all have at most this many
+                              intervals run one lane per pair (0 = 8) */
+    uint32_t search_min;   /* batched: streamed lists longer than this are first narrowed
+                              to the resident list's Hilbert range by a 64-ary search
+                              (0 = 1024) */
+    uint32_t reserved;     /* must be 0 */
+    void *d_workspace;     /* batched: device scratch of april_filter_workspace_size()
+                              bytes, or NULL to let the library allocate (stream-ordered);
+                              pass one to capture the call in a hipGraph */
+    uint64_t workspace_bytes;
 } april_filter_opts_t;
 
 /*
+ * Device scratch the batched schedule needs for n_pairs pairs: the
+ * workgroup queue (4 bytes per pair) and a few counters.
+ */
+int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opts, uint64_t *bytes);
+
+/*
  * The intermediate filter (Sec. 4.2, Alg. 2) on n_pairs candidate pairs.
+ *
+ * Schedules (the verdicts are identical):
+ *   APRIL_SCHED_PLAIN    one wavefront per pair; the three joins run as
+ *                        merge paths over LDS tiles of both lists.
+ *   APRIL_SCHED_BATCHED  a binning kernel sorts pairs into three queues by
+ *                        list length (lane per pair / wavefront per pair /
+ *                        workgroup per pair), then one persistent kernel
+ *                        drains them: the shorter side's lists stay in LDS
+ *                        (and are reused by consecutive pairs sharing that
+ *                        object), the other side's lists are streamed in
+ *                        coalesced chunks.  Launches only kernels when a
+ *                        workspace is passed, so it can be captured in a
+ *                        hipGraph.
  *   R, S        device-resident lists on the same grid (else APRIL_E_GRID)
  *   d_r, d_s    device uint32[n_pairs]: pair p is (R object d_r[p], S object d_s[p])
  *   d_verdict   device uint8[n_pairs]: APRIL_TN / APRIL_TH / APRIL_INDECISIVE,
@@ -184,8 +218,11 @@ int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, const uint3
 /*
  * Candidate pairs of the MBR filter step (Sec. 2): every (r, s) whose closed
  * bounding rectangles intersect.  Boxes are host float64 [n][4] =
- * (xmin, ymin, xmax, ymax).  Pairs are written sorted by (r, s) to the host
- * arrays r_out, s_out of `capacity` entries; *n_out receives the count.  If
+ * (xmin, ymin, xmax, ymax).  Pairs are written to the host arrays r_out,
+ * s_out of `capacity` entries, grouped by r, the r objects in the Z-order of
+ * their MBR centres and s ascending within each r -- pairs close in the
+ * output are close in space, which lets the filter reuse cached lists;
+ * *n_out receives the count.  If
  * capacity is too small nothing is written, *n_out holds the required count
  * and APRIL_E_NOMEM is returned.  Host, multi-threaded.
  */

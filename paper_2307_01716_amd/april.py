@@ -47,7 +47,9 @@ class april_lists_info_t(C.Structure):
 
 class april_filter_opts_t(C.Structure):
     _fields_ = [("schedule", C.c_uint32), ("flags", C.c_uint32), ("waves", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("tile", C.c_uint32), ("chunk", C.c_uint32), ("thread_max", C.c_uint32),
+                ("search_min", C.c_uint32), ("reserved", C.c_uint32),
+                ("d_workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
 
 
 class april_device_info_t(C.Structure):
@@ -86,12 +88,13 @@ def lib():
     L.april_lists_free.restype = None
     L.april_filter_pairs.argtypes = [P, P, P, P, u64, P, P, C.POINTER(april_filter_opts_t), P]
     L.april_alg2_bytes.argtypes = [P, P, P, P, u64, P, P]
+    L.april_filter_workspace_size.argtypes = [u64, C.POINTER(april_filter_opts_t), C.POINTER(u64)]
     L.april_mbr_join.argtypes = [P, u64, P, u64, P, P, u64, C.POINTER(u64)]
     L.april_device_info.argtypes = [C.POINTER(april_device_info_t)]
     L.april_last_error.restype = C.c_char_p
     for name in ("april_build_lists", "april_lists_from_arrays", "april_lists_info",
                  "april_lists_export", "april_lists_to_device", "april_filter_pairs",
-                 "april_alg2_bytes",
+                 "april_alg2_bytes", "april_filter_workspace_size",
                  "april_mbr_join", "april_device_info"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -208,12 +211,28 @@ def april_lists_to_device(host: Lists, codec: int = CODEC_RAW, stream=None) -> L
     return Lists(h.value, keep=host)
 
 
+def _opts(schedule=SCHED_PLAIN, flags=0, waves=0, tile=0, chunk=0, thread_max=0, search_min=0,
+          workspace=None):
+    ws = _dptr(workspace) if workspace is not None else None
+    nbytes = int(workspace.numel() * workspace.element_size()) if hasattr(workspace, "numel") else 0
+    return april_filter_opts_t(schedule, flags, waves, tile, chunk, thread_max, search_min,
+                               0, ws, nbytes)
+
+
+def april_filter_workspace_size(n_pairs: int, schedule=SCHED_BATCHED) -> int:
+    o = _opts(schedule)
+    out = C.c_uint64()
+    _check(lib().april_filter_workspace_size(n_pairs, C.byref(o), C.byref(out)))
+    return out.value
+
+
 def april_filter_pairs(R: Lists, S: Lists, r, s, verdict, counts=None, schedule=SCHED_PLAIN,
-                       flags=0, waves=0, stream=None) -> int:
+                       flags=0, waves=0, stream=None, **tuning) -> int:
     """r, s: int32/uint32 device tensors [P]; verdict: uint8 device tensor [P];
-    counts: int64 device tensor [3] or None."""
+    counts: int64 device tensor [3] or None.  `tuning` keys: tile, chunk,
+    thread_max, search_min, workspace (a device tensor)."""
     n = int(r.numel()) if hasattr(r, "numel") else (0 if isinstance(r, int) else int(len(r)))
-    opts = april_filter_opts_t(schedule, flags, waves, 0)
+    opts = _opts(schedule, flags, waves, **tuning)
     return _check(lib().april_filter_pairs(R.handle, S.handle, _dptr(r), _dptr(s), n,
                                            _dptr(verdict), _dptr(counts), C.byref(opts),
                                            _stream(stream)))
@@ -227,7 +246,8 @@ def april_alg2_bytes(R: Lists, S: Lists, r, s, bytes_out, stream=None) -> int:
 
 
 def april_mbr_join(boxes_r: np.ndarray, boxes_s: np.ndarray):
-    """Candidate pairs (r, s) of intersecting closed MBRs, sorted by (r, s)."""
+    """Candidate pairs (r, s) of intersecting closed MBRs, grouped by r with the
+    r objects in the Z-order of their MBR centres (s ascending within r)."""
     br = np.ascontiguousarray(boxes_r, np.float64)
     bs = np.ascontiguousarray(boxes_s, np.float64)
     need = C.c_uint64()

@@ -1,0 +1,71 @@
+// Device-side pieces shared by the filter kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "april.h"
+
+namespace april {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+struct ListView {
+    const uint64_t *off;
+    const uint32_t *s;
+    const uint32_t *e;
+};
+
+struct FilterArgs {
+    ListView Ar, Fr, As, Fs;
+    const uint32_t *r;
+    const uint32_t *s;
+    uint64_t n_pairs;
+    uint64_t n_r, n_s;
+    uint8_t *verdict;
+    unsigned long long *counts;
+};
+
+// Make this wave's LDS writes visible to its own later LDS reads (and keep
+// the compiler from moving LDS accesses across this point).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Alg. 2's IntervalJoin run sequentially by one lane; *rx, *ry receive how
+// many leading elements of X and Y the loop read.
+__device__ inline bool seq_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
+                         uint32_t n, const uint32_t *__restrict__ ys,
+                         const uint32_t *__restrict__ ye, uint32_t m, uint32_t *rx, uint32_t *ry) {
+    uint32_t i = 0, j = 0, ri = 0, rj = 0;
+    bool found = false;
+    while (i < n && j < m) {
+        ri = i + 1;
+        rj = j + 1;
+        const uint32_t a = xs[i], b = xe[i], c = ys[j], d = ye[j];
+        if (a < d && c < b) { found = true; break; }
+        if (b <= d) i++;
+        else j++;
+    }
+    *rx = ri;
+    *ry = rj;
+    return found;
+}
+
+
+// Batched schedule (batched.hip): scratch bytes for n_pairs, and the launch
+// of its binning and persistent kernels on `workspace`.
+uint64_t batched_workspace_bytes(uint64_t n_pairs);
+// XCDs of a device with `cus` compute units (32 CUs each on gfx950)
+int xcd_count(int cus);
+int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
+                   hipStream_t stream);
+
+}  // namespace april

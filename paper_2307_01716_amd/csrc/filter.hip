@@ -23,46 +23,17 @@
 
 #include <algorithm>
 
+#include "device.hpp"
 #include "internal.hpp"
 
 namespace april {
 namespace {
 
-constexpr int kWave = 64;
-constexpr int kWavesPerBlock = 4;
-constexpr int kBlock = kWave * kWavesPerBlock;
-
-struct ListView {
-    const uint64_t *off;
-    const uint32_t *s;
-    const uint32_t *e;
-};
-
-struct FilterArgs {
-    ListView Ar, Fr, As, Fs;
-    const uint32_t *r;
-    const uint32_t *s;
-    uint64_t n_pairs;
-    uint64_t n_r, n_s;
-    uint8_t *verdict;
-    unsigned long long *counts;
-};
-
-// Make this wave's LDS writes visible to its own later LDS reads (and keep
-// the compiler from moving LDS accesses across this point).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
 // Any overlap between X = [xs, xe)[0..n) and Y = [ys, ye)[0..m)?  Result is
 // the one Alg. 2's IntervalJoin returns.  lx, ly: this wave's LDS tiles of
 // 64*K entries each.
 template <int K>
-__device__ bool wave_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
+__device__ __forceinline__ bool wave_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
                           uint32_t n, const uint32_t *__restrict__ ys,
                           const uint32_t *__restrict__ ye, uint32_t m, uint2 *lx, uint2 *ly,
                           uint32_t lane) {
@@ -106,15 +77,20 @@ __device__ bool wave_join(const uint32_t *__restrict__ xs, const uint32_t *__res
     return false;
 }
 
+// Workgroups are dealt to the XCDs round-robin, so workgroup b runs on XCD
+// b % xcds; each XCD takes one contiguous range of the pairs, keeping pairs
+// that are close in the input (and share lists) in one L2.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_filter_plain(FilterArgs a) {
+__global__ __launch_bounds__(kBlock) void k_filter_plain(FilterArgs a, uint32_t xcds) {
     __shared__ uint2 lds[kWavesPerBlock][2][kWave * K];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t w = uniform(threadIdx.x / kWave);
     uint2 *lx = lds[w][0], *ly = lds[w][1];
-    const uint64_t n_waves = uint64_t(gridDim.x) * kWavesPerBlock;
+    const uint32_t xcd = blockIdx.x % xcds, bx = blockIdx.x / xcds, nbx = gridDim.x / xcds;
+    const uint64_t lo = a.n_pairs * xcd / xcds, hi = a.n_pairs * (xcd + 1) / xcds;
+    const uint64_t n_waves = uint64_t(nbx) * kWavesPerBlock;
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
-    for (uint64_t p = uint64_t(blockIdx.x) * kWavesPerBlock + w; p < a.n_pairs; p += n_waves) {
+    for (uint64_t p = lo + uint64_t(bx) * kWavesPerBlock + w; p < hi; p += n_waves) {
         const uint32_t r = uniform(a.r[p]), s = uniform(a.s[p]);
         uint8_t v;
         if (r >= a.n_r || s >= a.n_s) {
@@ -148,26 +124,6 @@ __global__ __launch_bounds__(kBlock) void k_filter_plain(FilterArgs a) {
         if (c_th) atomicAdd(&a.counts[1], c_th);
         if (c_ind) atomicAdd(&a.counts[2], c_ind);
     }
-}
-
-// Alg. 2's IntervalJoin run sequentially by one lane; *rx, *ry receive how
-// many leading elements of X and Y the loop read.
-__device__ bool seq_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
-                         uint32_t n, const uint32_t *__restrict__ ys,
-                         const uint32_t *__restrict__ ye, uint32_t m, uint32_t *rx, uint32_t *ry) {
-    uint32_t i = 0, j = 0, ri = 0, rj = 0;
-    bool found = false;
-    while (i < n && j < m) {
-        ri = i + 1;
-        rj = j + 1;
-        const uint32_t a = xs[i], b = xe[i], c = ys[j], d = ye[j];
-        if (a < d && c < b) { found = true; break; }
-        if (b <= d) i++;
-        else j++;
-    }
-    *rx = ri;
-    *ry = rj;
-    return found;
 }
 
 // One lane per pair: the verdict of Alg. 2 and the bytes it moves --
@@ -218,10 +174,7 @@ __global__ void k_check_pairs(const uint32_t *r, const uint32_t *s, uint64_t n, 
         if (r[p] >= n_r || s[p] >= n_s) atomicOr(bad, 1u);
 }
 
-struct DeviceState {
-    int cus = 0;
-    unsigned int *flag = nullptr;   // one word for index validation
-};
+}  // namespace
 
 int device_state(DeviceState **out) {
     static DeviceState states[64];
@@ -241,7 +194,6 @@ int device_state(DeviceState **out) {
     return APRIL_OK;
 }
 
-}  // namespace
 }  // namespace april
 
 using namespace april;
@@ -301,16 +253,21 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
     if (n_pairs && (!d_r || !d_s || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
     april_filter_opts_t o{};
     if (opts) o = *opts;
-    if (o.schedule != APRIL_SCHED_PLAIN) return fail(APRIL_E_INVALID, "unknown schedule");
+    if (o.schedule != APRIL_SCHED_PLAIN && o.schedule != APRIL_SCHED_BATCHED)
+        return fail(APRIL_E_INVALID, "unknown schedule");
+    if (R->n >= 0x7fffffffull || S->n >= 0x7fffffffull)
+        return fail(APRIL_E_INVALID, "collections must hold fewer than 2^31 - 1 objects");
     DeviceState *st;
     if (int rc = device_state(&st)) return rc;
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     auto *counts = reinterpret_cast<unsigned long long *>(d_counts);
-    if (counts) {
-        k_zero_counts<<<1, 64, 0, stream>>>(counts);
-        APRIL_HIP_TRY(hipGetLastError());
+    if (n_pairs == 0) {
+        if (counts) {
+            k_zero_counts<<<1, 64, 0, stream>>>(counts);
+            APRIL_HIP_TRY(hipGetLastError());
+        }
+        return APRIL_OK;
     }
-    if (n_pairs == 0) return APRIL_OK;
     if (o.flags & APRIL_VALIDATE) {
         APRIL_HIP_TRY(hipMemsetAsync(st->flag, 0, sizeof(unsigned int), stream));
         k_check_pairs<<<1024, 256, 0, stream>>>(d_r, d_s, n_pairs, R->n, S->n, st->flag);
@@ -321,10 +278,37 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
         if (bad) return fail(APRIL_E_INVALID, "pair index out of range");
     }
     FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, d_verdict, counts);
+    if (o.schedule == APRIL_SCHED_BATCHED) {
+        const uint64_t need = batched_workspace_bytes(n_pairs);
+        if (o.d_workspace) {
+            if (o.workspace_bytes < need) return fail(APRIL_E_INVALID, "workspace too small");
+            return launch_batched(a, o, st->cus, o.d_workspace, stream);
+        }
+        void *ws = nullptr;
+        hipError_t e = hipMallocAsync(&ws, need, stream);
+        if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
+        const int rc = launch_batched(a, o, st->cus, ws, stream);
+        APRIL_HIP_TRY(hipFreeAsync(ws, stream));
+        return rc;
+    }
+    if (counts) {
+        k_zero_counts<<<1, 64, 0, stream>>>(counts);
+        APRIL_HIP_TRY(hipGetLastError());
+    }
     uint64_t waves = o.waves ? o.waves : uint64_t(st->cus) * 32;
     waves = std::min<uint64_t>(waves, n_pairs);
-    const uint64_t blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_filter_plain<4><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a);
+    const uint32_t xcds = uint32_t(xcd_count(st->cus));
+    uint64_t blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    blocks = (blocks + xcds - 1) / xcds * xcds;   // every XCD gets the same number of workgroups
+    k_filter_plain<4><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a, xcds);
     APRIL_HIP_TRY(hipGetLastError());
+    return APRIL_OK;
+}
+
+extern "C" int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opts,
+                                           uint64_t *bytes) {
+    clear_error();
+    if (!bytes) return fail(APRIL_E_INVALID, "NULL argument");
+    *bytes = (opts && opts->schedule == APRIL_SCHED_BATCHED) || !opts ? batched_workspace_bytes(n_pairs) : 0;
     return APRIL_OK;
 }

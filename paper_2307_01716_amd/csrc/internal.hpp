@@ -79,4 +79,12 @@ void parallel(int threads, F fn) {
 }
 int host_threads();
 
+// Per-device state of the filter: compute-unit count and a one-word flag
+// used by index validation.  Created on first use on each device.
+struct DeviceState {
+    int cus = 0;
+    unsigned int *flag = nullptr;
+};
+int device_state(DeviceState **out);
+
 }  // namespace april

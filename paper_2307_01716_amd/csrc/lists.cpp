@@ -140,6 +140,16 @@ int april_lists_from_arrays(const april_grid_t *grid, uint64_t n, const uint64_t
         };
         if (!check(off_a, start_a, end_a) || !check(off_f, start_f, end_f))
             return fail(APRIL_E_CORRUPT, "interval lists are not sorted and disjoint");
+        // every F interval lies inside one A interval (Full cells are cells
+        // of the polygon)
+        for (uint64_t k = 0; k < n; k++) {
+            uint64_t t = off_a[k];
+            for (uint64_t q = off_f[k]; q < off_f[k + 1]; q++) {
+                while (t < off_a[k + 1] && end_a[t] < end_f[q]) t++;
+                if (t == off_a[k + 1] || start_a[t] > start_f[q])
+                    return fail(APRIL_E_CORRUPT, "F-list not contained in the A-list");
+            }
+        }
     }
     auto *L = new (std::nothrow) april_lists;
     if (!L) return fail(APRIL_E_NOMEM, "out of host memory");
@@ -352,9 +362,22 @@ int april_mbr_join(const double *br, uint64_t nr, const double *bs, uint64_t ns,
     *n_out = total;
     if (total > capacity) return fail(APRIL_E_NOMEM, "pair capacity too small");
     if (total && (!r_out || !s_out)) return fail(APRIL_E_INVALID, "NULL output arrays");
+    // emit r objects in the Z-order of their MBR centres, so that pairs that
+    // are close in the output are close in space (their lists are shared)
+    std::vector<std::pair<uint64_t, uint32_t>> order(nr);
+    const double inv = ext > 0 ? 65535.0 / ext : 0.0;
+    for (uint64_t r = 0; r < nr; r++) {
+        const double *a = br + 4 * r;
+        const uint32_t qx = uint32_t(std::min(65535.0, std::max(0.0, ((a[0] + a[2]) * 0.5 - lo[0]) * inv)));
+        const uint32_t qy = uint32_t(std::min(65535.0, std::max(0.0, ((a[1] + a[3]) * 0.5 - lo[1]) * inv)));
+        uint64_t z = 0;
+        for (int b = 15; b >= 0; b--) z = (z << 2) | (uint64_t((qy >> b) & 1u) << 1) | ((qx >> b) & 1u);
+        order[r] = {z, uint32_t(r)};
+    }
+    std::sort(order.begin(), order.end());
     uint64_t t = 0;
-    for (uint64_t r = 0; r < nr; r++)
-        for (uint32_t s : per_r[r]) { r_out[t] = uint32_t(r); s_out[t] = s; t++; }
+    for (const auto &o : order)
+        for (uint32_t s : per_r[o.second]) { r_out[t] = o.second; s_out[t] = s; t++; }
     return APRIL_OK;
 }
 

@@ -14,5 +14,5 @@ from .polygons import (  # noqa: F401
     snap,
 )
 from .grid import Grid, grid_covering  # noqa: F401
-from .intervals import random_lists, complement_list, ListSet  # noqa: F401
+from .intervals import random_lists, complement_list, sub_lists, ListSet  # noqa: F401
 from . import configs  # noqa: F401

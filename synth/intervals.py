@@ -68,3 +68,17 @@ def random_lists(rng: np.random.Generator, k: int, lo: int = 0, hi: int = 2 ** 3
 def complement_list(start: np.ndarray, end: np.ndarray):
     """Gaps between consecutive intervals: touches the list everywhere, overlaps nowhere."""
     return end[:-1].copy(), start[1:].copy()
+
+
+def sub_lists(rng: np.random.Generator, start: np.ndarray, end: np.ndarray, p: float = 0.5):
+    """A list inside (start, end): each interval is kept with probability p,
+    shrunk to a random non-empty sub-interval.  Used as an F-list for the
+    A-list (start, end)."""
+    start = np.asarray(start, dtype=np.int64)
+    end = np.asarray(end, dtype=np.int64)
+    keep = rng.random(len(start)) < p
+    s0, e0 = start[keep], end[keep]
+    a = s0 + (rng.random(len(s0)) * (e0 - s0)).astype(np.int64)
+    b = a + 1 + (rng.random(len(s0)) * (e0 - a)).astype(np.int64)
+    b = np.minimum(b, e0)
+    return a.astype(np.uint32), b.astype(np.uint32)

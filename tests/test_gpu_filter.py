@@ -21,7 +21,7 @@ import pytest
 
 import oracle
 import synth
-from synth.intervals import ListSet, complement_list, random_lists
+from synth.intervals import ListSet, complement_list, random_lists, sub_lists
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,19 @@ def gpu_filter(LRd, LSd, r, s, **kw):
 
 GRID = (0.0, 0.0, float(1 << 16) * 2.0 ** -30 * (1 << 16), 16)
 
+# schedules under test: plain, batched with defaults, and batched tunings
+# that push pairs through every bin and code path (lane-per-pair bin, wave
+# bin with either side resident, workgroup bin with multi-tile residents,
+# range search on every streamed list)
+SCHEDULES = {
+    "plain": dict(schedule=april.SCHED_PLAIN),
+    "batched": dict(schedule=april.SCHED_BATCHED),
+    "batched-small-tiles": dict(schedule=april.SCHED_BATCHED, tile=128, chunk=1, thread_max=100,
+                                search_min=64),
+    "batched-wide": dict(schedule=april.SCHED_BATCHED, tile=512, chunk=4, thread_max=1,
+                         search_min=1),
+}
+
 
 def _random_collection(rng, n, kind):
     A, F = [], []
@@ -76,7 +89,7 @@ def _random_collection(rng, n, kind):
         lo = int(rng.integers(0, 1 << 20))
         span = max(4 * L + 8, int(rng.integers(2 * L + 2, 64 * L + 64)))
         a = random_lists(rng, max(L, 1), lo, lo + span)
-        f = random_lists(rng, int(rng.integers(0, max(L // 2, 1) + 1)), lo, lo + span)
+        f = sub_lists(rng, *a, p=float(rng.random()))    # F inside A, as for polygons
         A.append(a)
         F.append(f)
     a = ListSet.from_lists(A)
@@ -84,27 +97,29 @@ def _random_collection(rng, n, kind):
     return oracle.Lists(a.off, a.start, a.end, f.off, f.start, f.end)
 
 
+@pytest.mark.parametrize("sched", list(SCHEDULES))
 @pytest.mark.parametrize("kind,n,P", [("mixed", 400, 20_000), ("edges", 300, 20_000),
                                       ("long", 12, 150)])
-def test_random_lists(kind, n, P):
+def test_random_lists(kind, n, P, sched):
     rng = np.random.default_rng({"mixed": 1, "edges": 2, "long": 3}[kind])
-    say(f"[random lists] kind={kind} n={n} P={P}")
+    say(f"[random lists] kind={kind} n={n} P={P} schedule={sched}")
     LR = _random_collection(rng, n, kind)
     LS = _random_collection(rng, n, kind)
     r = rng.integers(0, n, P).astype(np.uint32)
     s = rng.integers(0, n, P).astype(np.uint32)
     want = oracle.filter_pairs(LR, LS, r, s)
-    got, cnt = gpu_filter(device_lists(GRID, LR), device_lists(GRID, LS), r, s)
+    got, cnt = gpu_filter(device_lists(GRID, LR), device_lists(GRID, LS), r, s, **SCHEDULES[sched])
     assert np.array_equal(got, want)
     assert np.array_equal(cnt, np.bincount(want, minlength=3))
 
 
+@pytest.mark.parametrize("sched", list(SCHEDULES))
 @pytest.mark.parametrize("k", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 30_000, 300_000])
-def test_touching_lists(k):
+def test_touching_lists(k, sched):
     """X against its gaps: no overlap anywhere (a full merge), then the same
     with one gap widened by one cell at a random place (one overlap)."""
     rng = np.random.default_rng(k)
-    say(f"[touching] k={k}")
+    say(f"[touching] k={k} schedule={sched}")
     X = random_lists(rng, k + 1, 0, 8 * k + 64)
     C = complement_list(*X)
     C2 = (C[0].copy(), C[1].copy())
@@ -123,8 +138,11 @@ def test_touching_lists(k):
     s = np.arange(4, dtype=np.uint32)
     want = oracle.filter_pairs(LRo, LSo, r, s)
     assert want[0] == oracle.TN and want[1] == oracle.TH and want[3] == oracle.TH
-    got, cnt = gpu_filter(device_lists(GRID, LRo), device_lists(GRID, LSo), r, s)
+    got, cnt = gpu_filter(device_lists(GRID, LRo), device_lists(GRID, LSo), r, s, **SCHEDULES[sched])
     assert np.array_equal(got, want)
+    # roles swapped: the long list on the other side
+    got2, _ = gpu_filter(device_lists(GRID, LSo), device_lists(GRID, LRo), s, r, **SCHEDULES[sched])
+    assert np.array_equal(got2, want)
 
 
 @pytest.fixture(scope="module")
@@ -137,14 +155,15 @@ def tiny():
     return R, S, g, LR, LS, r, s, v, b
 
 
-def test_tiny_end_to_end(tiny):
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+def test_tiny_end_to_end(tiny, sched):
     R, S, g, LR, LS, r, s, v, b = tiny
-    say(f"[tiny] pairs={len(r)}")
+    say(f"[tiny] pairs={len(r)} schedule={sched}")
     hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
     hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
     dR = april.april_lists_to_device(hR)
     dS = april.april_lists_to_device(hS)
-    got, cnt = gpu_filter(dR, dS, r, s)
+    got, cnt = gpu_filter(dR, dS, r, s, **SCHEDULES[sched])
     assert np.array_equal(got, v)
     assert np.array_equal(cnt, np.bincount(v, minlength=3))
     by = torch.zeros(len(r), dtype=torch.int64, device="cuda")
@@ -165,24 +184,26 @@ def test_tiny_waves_and_duplicates(tiny):
         assert np.array_equal(cnt, np.bincount(v[perm], minlength=3))
 
 
-def test_empty_and_bad_pairs(tiny):
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+def test_empty_and_bad_pairs(tiny, sched):
     R, S, g, LR, LS, r, s, v, b = tiny
+    kw = SCHEDULES[sched]
     dR, dS = device_lists(g, LR), device_lists(g, LS)
-    say("[edge] no pairs")
-    got, cnt = gpu_filter(dR, dS, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    say(f"[edge] no pairs schedule={sched}")
+    got, cnt = gpu_filter(dR, dS, np.zeros(0, np.uint32), np.zeros(0, np.uint32), **kw)
     assert len(got) == 0 and np.array_equal(cnt, [0, 0, 0])
     say("[edge] out-of-range indices")
     rr = np.array([0, len(R), 5, 0xFFFFFFFF], np.uint32)
     ss = np.array([0, 0, len(S) + 3, 1], np.uint32)
-    got, cnt = gpu_filter(dR, dS, rr, ss)
+    got, cnt = gpu_filter(dR, dS, rr, ss, **kw)
     want0 = oracle.filter_pairs(LR, LS, rr[:1], ss[:1])[0]
     assert got[0] == want0
     assert list(got[1:]) == [april.BAD_PAIR] * 3
     assert cnt.sum() == 1
     with pytest.raises(april.AprilError) as e:
-        gpu_filter(dR, dS, rr, ss, flags=april.VALIDATE)
+        gpu_filter(dR, dS, rr, ss, flags=april.VALIDATE, **kw)
     assert e.value.code == april.E_INVALID
-    got, cnt = gpu_filter(dR, dS, r[:50], s[:50], flags=april.VALIDATE)
+    got, cnt = gpu_filter(dR, dS, r[:50], s[:50], flags=april.VALIDATE, **kw)
     assert np.array_equal(got, v[:50])
 
 
@@ -209,10 +230,16 @@ def scale():
     return R, S, g, r, s, dR, dS
 
 
-def test_scale_sampled_against_oracle(scale):
+@pytest.fixture(scope="module")
+def scale_plain(scale):
     R, S, g, r, s, dR, dS = scale
     say(f"[scale] plain filter over {len(r)} pairs")
-    got, cnt = gpu_filter(dR, dS, r, s)
+    return gpu_filter(dR, dS, r, s)
+
+
+def test_scale_sampled_against_oracle(scale, scale_plain):
+    R, S, g, r, s, dR, dS = scale
+    got, cnt = scale_plain
     assert np.array_equal(cnt, np.bincount(got, minlength=3))
     assert cnt.sum() == len(r)
     rng = np.random.default_rng(17)
@@ -233,3 +260,57 @@ def test_scale_swapped_roles(scale):
     a, _ = gpu_filter(dR, dS, r, s)
     b, _ = gpu_filter(dS, dR, s, r)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("sched", ["batched", "batched-small-tiles", "batched-wide"])
+def test_scale_batched_equals_plain(scale, scale_plain, sched):
+    """Full-size check of the batched schedule in the benchmark's launch
+    configuration: every verdict equals the plain kernel's (itself checked
+    against the oracle on a sample above)."""
+    R, S, g, r, s, dR, dS = scale
+    say(f"[scale] {sched} over {len(r)} pairs")
+    got, cnt = gpu_filter(dR, dS, r, s, **SCHEDULES[sched])
+    assert np.array_equal(got, scale_plain[0])
+    assert np.array_equal(cnt, scale_plain[1])
+
+
+def test_batched_workspace_and_graph(tiny):
+    """Batched schedule with a caller workspace, captured in a hipGraph and
+    replayed several times with eager work in between; every replay must give
+    the oracle's verdicts (the pair buffers are refilled between replays)."""
+    R, S, g, LR, LS, r, s, v, b = tiny
+    dR, dS = device_lists(g, LR), device_lists(g, LS)
+    P = len(r)
+    nbytes = april.april_filter_workspace_size(P)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    rt, st = cuda(r), cuda(s)
+    verdict = torch.empty(P, dtype=torch.uint8, device="cuda")
+    counts = torch.empty(3, dtype=torch.int64, device="cuda")
+    say("[graph] eager with workspace")
+    april.april_filter_pairs(dR, dS, rt, st, verdict, counts, schedule=april.SCHED_BATCHED,
+                             workspace=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(verdict.cpu().numpy(), v)
+    say("[graph] capture")
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            april.april_filter_pairs(dR, dS, rt, st, verdict, counts,
+                                     schedule=april.SCHED_BATCHED, workspace=ws,
+                                     stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    for rep in range(4):
+        perm = rng.permutation(P)
+        rt.copy_(cuda(r[perm]))
+        st.copy_(cuda(s[perm]))
+        verdict.fill_(99)
+        counts.fill_(-1)
+        torch.cuda.synchronize()
+        say(f"[graph] replay {rep}")
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(verdict.cpu().numpy(), v[perm]), rep
+        assert np.array_equal(counts.cpu().numpy(), np.bincount(v, minlength=3)), rep

@@ -74,10 +74,25 @@ def test_builder_matches_oracle_scale_sample():
     assert _same(april.april_build_lists(g, sub.xy, sub.voff, april.STRICT), oracle.build_lists(g, sub))
 
 
+def _by_rs(r, s):
+    k = np.lexsort((s, r))
+    return r[k], s[k]
+
+
+def _check_grouping(r, s):
+    # every r forms one contiguous run; s ascends within it
+    starts = np.flatnonzero(np.diff(r.astype(np.int64)) != 0) + 1
+    assert len(np.unique(r)) == len(starts) + 1
+    same = r[1:] == r[:-1]
+    assert np.all(s[1:][same] > s[:-1][same])
+
+
 def test_mbr_join_matches_oracle():
     R, S, g = synth.configs.tiny()
     r, s = april.april_mbr_join(R.mbrs(), S.mbrs())
     ro, so = oracle.mbr_join(R, S)
+    _check_grouping(r, s)
+    r, s = _by_rs(r, s)
     assert np.array_equal(r, ro) and np.array_equal(s, so)
 
 
@@ -86,6 +101,8 @@ def test_mbr_join_matches_oracle_scale():
     r, s = april.april_mbr_join(R.mbrs(), S.mbrs())
     ro, so = oracle.mbr_join(R, S)
     assert len(r) > 4_000_000
+    _check_grouping(r, s)
+    r, s = _by_rs(r, s)
     assert np.array_equal(r, ro) and np.array_equal(s, so)
 
 
@@ -149,6 +166,13 @@ def test_error_corrupt_lists():
     assert e.value.code == april.E_CORRUPT
     L = april.april_lists_from_arrays(G6, off, [3, 5], [4, 6], np.array([0, 0], np.uint64), [], [])
     assert L.info().n_a == 2 and L.info().n_f == 0
+    # an F interval that leaves its A interval: not an APRIL approximation
+    with pytest.raises(april.AprilError) as e:
+        april.april_lists_from_arrays(G6, off, [3, 10], [6, 20], np.array([0, 1], np.uint64), [5], [7])
+    assert e.value.code == april.E_CORRUPT
+    L = april.april_lists_from_arrays(G6, off, [3, 10], [6, 20], np.array([0, 2], np.uint64), [3, 12],
+                                      [5, 20])
+    assert L.info().n_f == 2
 
 
 def test_filter_rejects_host_lists():

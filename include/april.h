@@ -125,19 +125,34 @@ int april_lists_info(const april_lists_t *lists, april_lists_info_t *info);
 int april_lists_export(const april_lists_t *lists, uint64_t *off_a, uint32_t *start_a,
                        uint32_t *end_a, uint64_t *off_f, uint32_t *start_f, uint32_t *end_f);
 
-#define APRIL_CODEC_RAW 0u   /* SoA uint32 start[] / end[] + uint64 CSR offsets */
+#define APRIL_CODEC_RAW 0u    /* SoA uint32 start[] / end[] + uint64 CSR offsets */
+#define APRIL_CODEC_VBYTE 1u  /* delta + VByte byte streams (Sec. 5.1): per list the
+                                 sequence s_0 < e_0 < s_1 < ... stored as varint(s_0),
+                                 then varint(gap - 1) for every later value; 7 bits per
+                                 byte, low first, high bit = more bytes follow; plus a
+                                 block entry every 64 intervals (absolute first start
+                                 and byte offset) so decoding can begin mid-list.  The
+                                 kernels decode while joining. */
 
 /*
  * Upload host lists to the current HIP device in the layout the kernels
  * read (Sec. 4.1: per object a sorted interval sequence; here split into
- * SoA start[] and end[] arrays plus CSR offsets).  Allocates device memory
- * owned by *out; asynchronous on hip_stream (the host lists must stay alive
- * until the stream has passed the copy).  Free with april_lists_free.
+ * SoA start[] and end[] arrays plus CSR offsets, or compressed with
+ * APRIL_CODEC_VBYTE).  Allocates device memory owned by *out.  RAW copies are
+ * asynchronous on hip_stream (the host lists must stay alive until the
+ * stream has passed the copy); VBYTE encodes on the host and returns after
+ * the copy.  Free with april_lists_free.
  */
 int april_lists_to_device(const april_lists_t *host, uint32_t codec, void *hip_stream,
                           april_lists_t **out);
 
 void april_lists_free(april_lists_t *lists);
+
+/*
+ * Copy device lists back to new host lists, decoding compressed ones on the
+ * device (the decoder the filter kernels use).  Synchronous on hip_stream.
+ */
+int april_lists_download(const april_lists_t *device_lists, void *hip_stream, april_lists_t **out);
 
 /* ---------------------------------------------------------------- filter */
 #define APRIL_SCHED_PLAIN 0u    /* one wavefront per candidate pair */
@@ -228,6 +243,76 @@ int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, const uint3
  */
 int april_mbr_join(const double *boxes_r, uint64_t n_r, const double *boxes_s, uint64_t n_s,
                    uint32_t *r_out, uint32_t *s_out, uint64_t capacity, uint64_t *n_out);
+
+/* ------------------------------------------------------------- serving */
+/*
+ * Served selection queries (Sec. 4.3.1): query polygons arrive one by one;
+ * each is answered against a device-resident collection S -- the S objects
+ * whose MBRs meet the query's MBR, each with its verdict.  Requests are
+ * batched continuously: the query's lists are built on host threads, ready
+ * requests are packed into the next free slot (a batch with its own stream
+ * and device buffers) as long as the slot's memory holds their lists and an
+ * upper bound of their candidate pairs, and several slots run on the device
+ * at once.  A request that alone exceeds a slot's capacity fails with
+ * APRIL_E_NOMEM.
+ */
+typedef struct april_server april_server_t;
+
+typedef struct {
+    uint32_t mbr_grid;      /* cells per side of the uniform MBR index of S (0 = 1024) */
+    uint32_t slots;         /* batches in flight at once, one stream each (0 = 3) */
+    uint64_t mem_budget;    /* device bytes for all slots' buffers (0 = 2 GiB) */
+    uint32_t max_batch;     /* queries per batch at most (0 = 8192) */
+    uint32_t host_threads;  /* query-list builder threads (0 = host cores - 2) */
+    april_filter_opts_t filter;   /* batched-filter tuning (schedule/workspace ignored) */
+} april_serve_opts_t;
+
+typedef struct {
+    int32_t status;          /* APRIL_OK, APRIL_PENDING, or the request's error code */
+    uint32_t reserved;
+    uint64_t n_pairs;        /* S objects whose MBR meets the query's MBR */
+    const uint32_t *s_ids;   /* host, ascending; valid until april_serve_release */
+    const uint8_t *verdict;  /* host; verdict[k] belongs to s_ids[k] */
+    uint64_t counts[3];      /* TN, TH, INDECISIVE */
+    double t_submit, t_built, t_done;   /* steady-clock seconds: submitted, lists
+                                           built, result ready */
+} april_result_t;
+
+typedef struct {
+    uint32_t slots, slots_busy;
+    uint64_t queued, ready;  /* requests waiting for a builder / for a slot */
+    uint64_t cap_pairs, cap_intervals, cap_queries;   /* per slot */
+} april_serve_stats_t;
+
+/*
+ * S_dev: device lists of S (borrowed: must outlive the server); s_boxes:
+ * host float64 [n][4] MBRs of S, copied.  Allocates the MBR index and every
+ * slot's buffers up front (no device allocation afterwards) and starts the
+ * builder and dispatcher threads.
+ */
+int april_serve_create(const april_lists_t *S_dev, const double *s_boxes,
+                       const april_serve_opts_t *opts, april_server_t **out);
+
+/* Queue a query polygon (xy copied; >= 3 vertices, on S's grid).  Returns at once. */
+int april_serve_submit(april_server_t *server, const double *xy, uint64_t n_vertices,
+                       uint64_t *ticket);
+
+/* APRIL_PENDING (1) until the result is ready, then APRIL_OK with *out filled. */
+int april_serve_poll(april_server_t *server, uint64_t ticket, april_result_t *out);
+
+/* Like poll, waiting up to timeout_s seconds. */
+int april_serve_wait(april_server_t *server, uint64_t ticket, double timeout_s, april_result_t *out);
+
+/* Drop a finished request and its result buffers. */
+int april_serve_release(april_server_t *server, uint64_t ticket);
+
+/* Forget a request; one already on the device is dropped when its batch ends. */
+int april_serve_cancel(april_server_t *server, uint64_t ticket);
+
+int april_serve_stats(april_server_t *server, april_serve_stats_t *stats);
+
+/* Finish batches in flight, stop the threads, free everything. */
+void april_serve_destroy(april_server_t *server);
 
 /* ---------------------------------------------------------------- misc */
 typedef struct {

@@ -21,7 +21,7 @@ OK, PENDING = 0, 1
 E_INVALID, E_GRID, E_NOMEM, E_HIP, E_CORRUPT, E_NODEV = -1, -2, -3, -4, -5, -6
 TN, TH, INDECISIVE, BAD_PAIR = 0, 1, 2, 255
 STRICT = 1
-CODEC_RAW = 0
+CODEC_RAW, CODEC_VBYTE = 0, 1
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 VALIDATE = 1
 
@@ -58,6 +58,25 @@ class april_device_info_t(C.Structure):
                 ("hbm_bytes", C.c_uint64), ("arch", C.c_char * 64), ("name", C.c_char * 128)]
 
 
+class april_serve_opts_t(C.Structure):
+    _fields_ = [("mbr_grid", C.c_uint32), ("slots", C.c_uint32), ("mem_budget", C.c_uint64),
+                ("max_batch", C.c_uint32), ("host_threads", C.c_uint32),
+                ("filter", april_filter_opts_t)]
+
+
+class april_result_t(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_uint32), ("n_pairs", C.c_uint64),
+                ("s_ids", C.POINTER(C.c_uint32)), ("verdict", C.POINTER(C.c_uint8)),
+                ("counts", C.c_uint64 * 3), ("t_submit", C.c_double), ("t_built", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class april_serve_stats_t(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("slots_busy", C.c_uint32), ("queued", C.c_uint64),
+                ("ready", C.c_uint64), ("cap_pairs", C.c_uint64), ("cap_intervals", C.c_uint64),
+                ("cap_queries", C.c_uint64)]
+
+
 _lib = None
 _exiting = False
 
@@ -84,6 +103,7 @@ def lib():
     L.april_lists_info.argtypes = [P, C.POINTER(april_lists_info_t)]
     L.april_lists_export.argtypes = [P] * 7
     L.april_lists_to_device.argtypes = [P, u32, P, C.POINTER(P)]
+    L.april_lists_download.argtypes = [P, P, C.POINTER(P)]
     L.april_lists_free.argtypes = [P]
     L.april_lists_free.restype = None
     L.april_filter_pairs.argtypes = [P, P, P, P, u64, P, P, C.POINTER(april_filter_opts_t), P]
@@ -91,11 +111,23 @@ def lib():
     L.april_filter_workspace_size.argtypes = [u64, C.POINTER(april_filter_opts_t), C.POINTER(u64)]
     L.april_mbr_join.argtypes = [P, u64, P, u64, P, P, u64, C.POINTER(u64)]
     L.april_device_info.argtypes = [C.POINTER(april_device_info_t)]
+    L.april_serve_create.argtypes = [P, P, C.POINTER(april_serve_opts_t), C.POINTER(P)]
+    L.april_serve_submit.argtypes = [P, P, u64, C.POINTER(u64)]
+    L.april_serve_poll.argtypes = [P, u64, C.POINTER(april_result_t)]
+    L.april_serve_wait.argtypes = [P, u64, C.c_double, C.POINTER(april_result_t)]
+    L.april_serve_release.argtypes = [P, u64]
+    L.april_serve_cancel.argtypes = [P, u64]
+    L.april_serve_stats.argtypes = [P, C.POINTER(april_serve_stats_t)]
+    L.april_serve_destroy.argtypes = [P]
+    L.april_serve_destroy.restype = None
     L.april_last_error.restype = C.c_char_p
     for name in ("april_build_lists", "april_lists_from_arrays", "april_lists_info",
-                 "april_lists_export", "april_lists_to_device", "april_filter_pairs",
+                 "april_lists_export", "april_lists_to_device", "april_lists_download",
+                 "april_filter_pairs",
                  "april_alg2_bytes", "april_filter_workspace_size",
-                 "april_mbr_join", "april_device_info"):
+                 "april_mbr_join", "april_device_info", "april_serve_create",
+                 "april_serve_submit", "april_serve_poll", "april_serve_wait", "april_serve_release",
+                 "april_serve_cancel", "april_serve_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -226,6 +258,13 @@ def april_filter_workspace_size(n_pairs: int, schedule=SCHED_BATCHED) -> int:
     return out.value
 
 
+def april_lists_download(dev: Lists, stream=None) -> Lists:
+    """Device lists back to host lists (compressed ones decoded on the device)."""
+    h = C.c_void_p()
+    _check(lib().april_lists_download(dev.handle, _stream(stream), C.byref(h)))
+    return Lists(h.value)
+
+
 def april_filter_pairs(R: Lists, S: Lists, r, s, verdict, counts=None, schedule=SCHED_PLAIN,
                        flags=0, waves=0, stream=None, **tuning) -> int:
     """r, s: int32/uint32 device tensors [P]; verdict: uint8 device tensor [P];
@@ -268,3 +307,78 @@ def april_device_info() -> dict:
     return {"device": inf.device, "compute_units": inf.compute_units,
             "wavefront_size": inf.wavefront_size, "hbm_bytes": inf.hbm_bytes,
             "arch": inf.arch.decode(), "name": inf.name.decode()}
+
+
+class Result:
+    """A finished request: S ids (ascending) with their verdicts, copied out."""
+
+    def __init__(self, r: april_result_t):
+        self.status = r.status
+        n = int(r.n_pairs)
+        self.s_ids = np.ctypeslib.as_array(r.s_ids, shape=(n,)).copy() if n else np.zeros(0, np.uint32)
+        self.verdict = np.ctypeslib.as_array(r.verdict, shape=(n,)).copy() if n else np.zeros(0, np.uint8)
+        self.counts = [int(c) for c in r.counts]
+        self.t_submit, self.t_built, self.t_done = r.t_submit, r.t_built, r.t_done
+
+    @property
+    def latency(self):
+        return self.t_done - self.t_submit
+
+
+class Server:
+    """april_serve_* on a device-resident collection S (see include/april.h)."""
+
+    def __init__(self, S_dev: Lists, s_boxes: np.ndarray, mbr_grid=0, slots=0, mem_budget=0,
+                 max_batch=0, host_threads=0, **tuning):
+        self._S = S_dev
+        boxes = np.ascontiguousarray(s_boxes, np.float64)
+        o = april_serve_opts_t(mbr_grid, slots, mem_budget, max_batch, host_threads,
+                               _opts(SCHED_BATCHED, **tuning))
+        h = C.c_void_p()
+        _check(lib().april_serve_create(S_dev.handle, _np(boxes), C.byref(o), C.byref(h)))
+        self._h = h.value
+
+    def submit(self, xy: np.ndarray) -> int:
+        xy = np.ascontiguousarray(xy, np.float64)
+        t = C.c_uint64()
+        _check(lib().april_serve_submit(self._h, _np(xy), len(xy), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; a Result (status OK) when done; raises on failure."""
+        r = april_result_t()
+        rc = lib().april_serve_poll(self._h, ticket, C.byref(r))
+        if rc == PENDING:
+            return None
+        _check(rc)
+        return Result(r)
+
+    def wait(self, ticket: int, timeout: float = 60.0):
+        r = april_result_t()
+        rc = lib().april_serve_wait(self._h, ticket, timeout, C.byref(r))
+        if rc == PENDING:
+            raise TimeoutError(f"ticket {ticket} still pending after {timeout}s")
+        _check(rc)
+        return Result(r)
+
+    def release(self, ticket: int):
+        _check(lib().april_serve_release(self._h, ticket))
+
+    def cancel(self, ticket: int):
+        _check(lib().april_serve_cancel(self._h, ticket))
+
+    def stats(self) -> dict:
+        st = april_serve_stats_t()
+        _check(lib().april_serve_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in april_serve_stats_t._fields_}
+
+    def close(self):
+        if self._h and not _exiting:
+            lib().april_serve_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

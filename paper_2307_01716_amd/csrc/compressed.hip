@@ -1,0 +1,266 @@
+// The filter on delta + VByte compressed lists (Sec. 5.1: join while
+// decoding, so an early exit leaves the rest of a list undecoded).
+//
+// One wavefront per pair, pairs taken 64 at a time from per-XCD contiguous
+// ranges like the raw batched schedule.  The three joins of Alg. 2 run in
+// order, X being the side with the shorter lists and Y the other:
+// X.A x Y.A, then X.A x Y.F and X.F x Y.A (AF and FA in r/s terms).  A join
+// decodes X tile by tile into LDS (up to TILE intervals); for each tile the
+// Y intervals that can meet it -- from the last block whose first start is at
+// or before the tile's first start, until a Y start reaches the tile's end --
+// are decoded window by window into a small LDS buffer and every lane
+// binary-searches the tile for its Y interval (the overlap test of the raw
+// batched kernel).  A ballot after each window ends the join early.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.hpp"
+#include "internal.hpp"
+#include "vbyte.hpp"
+
+namespace april {
+namespace {
+
+struct CList {
+    const uint64_t *off, *boff, *blk;
+    const uint8_t *bytes;
+    const uint32_t *bval, *bpos;
+};
+
+struct CArgs {
+    CList Ar, Fr, As, Fs;
+    const uint32_t *r, *s;
+    uint64_t n_pairs, n_r, n_s;
+    uint8_t *verdict;
+    unsigned long long *counts;
+    unsigned int *xhead;
+    uint32_t xcds;
+    uint32_t search_min;
+};
+
+__device__ __forceinline__ uint32_t first_gt(const uint32_t *__restrict__ arr, uint32_t m, uint32_t key,
+                                             uint32_t lane) {
+    // first j in [0, m) with arr[j] > key (m if none): 64-ary search
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 64) {
+        const uint64_t step = (uint64_t(hi - lo) + 63) >> 6;
+        const uint64_t probe = lo + (lane + 1) * step - 1;
+        const bool pred = probe >= hi ? true : (arr[probe] > key);
+        const uint64_t mask = __ballot(pred);
+        if (!mask) { lo = hi; break; }
+        const uint64_t f = __builtin_ctzll(mask);
+        const uint64_t pf = lo + (f + 1) * step - 1;
+        const uint32_t nlo = uint32_t(lo + f * step);
+        hi = pf < hi ? uint32_t(pf) : hi;
+        lo = nlo;
+    }
+    if (hi == lo) return lo;
+    const uint32_t j = lo + lane;
+    const bool pred = j >= hi ? true : (arr[j] > key);
+    const uint64_t mask = __ballot(pred);
+    return mask ? lo + uint32_t(__builtin_ctzll(mask)) : hi;
+}
+
+struct ListRef {
+    CList L;
+    uint32_t obj, n;
+};
+
+__device__ __forceinline__ VCursor cursor_at(const ListRef &x) {
+    return vcursor(x.L.bytes, x.L.boff[x.obj], x.L.boff[x.obj + 1], x.n);
+}
+
+// Any overlap between list X (tiled through LDS) and list Y (streamed)?
+template <int TILE>
+__device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t *te, uint32_t *ys,
+                      uint32_t *ye, uint32_t search_min, uint32_t lane) {
+    if (X.n == 0 || Y.n == 0) return false;
+    VCursor cx = cursor_at(X);
+    const uint64_t yb0 = Y.L.boff[Y.obj], yb1 = Y.L.boff[Y.obj + 1];
+    const uint64_t yblk = Y.L.blk[Y.obj];
+    const uint32_t ynblk = uint32_t(Y.L.blk[Y.obj + 1] - yblk);
+    while (cx.g < cx.nvals) {
+        // fill the tile window by window (a window completes at most 128
+        // intervals and may leave one start pending after them)
+        uint32_t nt = 0;
+        while (cx.g < cx.nvals && nt + 130 <= TILE) {
+            wave_lds_sync();
+            nt += vdecode_window(cx, ts + nt, te + nt, false, lane);
+        }
+        wave_lds_sync();
+        if (nt) {
+            const uint32_t x_lo = ts[0], x_hi = te[nt - 1];
+            // Y from the last block whose first start is at or before x_lo
+            VCursor cy = vcursor(Y.L.bytes, yb0, yb1, Y.n);
+            if (Y.n > search_min && ynblk > 1) {
+                uint32_t b = first_gt(Y.L.bval + yblk, ynblk, x_lo, lane);
+                b = b ? b - 1 : 0;
+                if (b) cy = vcursor_block(Y.L.bytes, yb0, yb1, Y.n, b, Y.L.bval[yblk + b], Y.L.bpos[yblk + b]);
+            }
+            while (cy.g < cy.nvals) {
+                wave_lds_sync();
+                const uint32_t k = vdecode_window(cy, ys, ye, true, lane);
+                wave_lds_sync();
+                bool hit = false;
+                for (uint32_t t = lane; t < k; t += 64) {
+                    const uint32_t s = ys[t], e = ye[t];
+                    uint32_t pos = 0;
+                    for (uint32_t step = 1u << (31 - __builtin_clz(nt)); step; step >>= 1) {
+                        const uint32_t q = pos + step;
+                        if (q <= nt && te[q - 1] <= s) pos = q;
+                    }
+                    hit |= pos < nt && ts[pos] < e;
+                }
+                if (__any(hit)) return true;
+                // every later Y interval starts after this tile ends
+                if (k == 0 || ys[k - 1] >= x_hi) break;
+            }
+        }
+        // a start decoded after the tile's last full interval opens the next tile
+        if (cx.g & 1u) {
+            const uint32_t pend = ts[nt];
+            wave_lds_sync();
+            if (lane == 0) ts[0] = pend;
+        }
+    }
+    return false;
+}
+
+template <int TILE>
+__global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
+    __shared__ uint32_t lds[kWavesPerBlock][2 * TILE + 2 * 132];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = uniform(threadIdx.x >> 6);
+    uint32_t *ts = lds[w], *te = ts + TILE, *ys = te + TILE, *ye = ys + 132;
+    unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
+    const uint32_t my_xcd = blockIdx.x % a.xcds;
+    for (uint32_t k = 0; k < a.xcds; k++) {
+        const uint32_t seg = (my_xcd + k) % a.xcds;
+        const uint64_t lo = a.n_pairs * seg / a.xcds, hi = a.n_pairs * (seg + 1) / a.xcds;
+        for (;;) {
+            unsigned int got = 0;
+            if (lane == 0) got = atomicAdd(&a.xhead[seg], 64u);
+            const uint64_t g0 = lo + uniform(__shfl(got, 0));
+            if (g0 >= hi) break;
+            const uint32_t cnt = uint32_t(min<uint64_t>(64, hi - g0));
+            for (uint32_t i = 0; i < cnt; i++) {
+                const uint64_t p = g0 + i;
+                const uint32_t r = uniform(a.r[p]), s = uniform(a.s[p]);
+                if (r >= a.n_r || s >= a.n_s) {
+                    if (lane == 0) a.verdict[p] = APRIL_BAD_PAIR;
+                    continue;
+                }
+                const uint32_t nar = uint32_t(a.Ar.off[r + 1] - a.Ar.off[r]);
+                const uint32_t nfr = uint32_t(a.Fr.off[r + 1] - a.Fr.off[r]);
+                const uint32_t nas = uint32_t(a.As.off[s + 1] - a.As.off[s]);
+                const uint32_t nfs = uint32_t(a.Fs.off[s + 1] - a.Fs.off[s]);
+                const bool xs = max(nas, nfs) < max(nar, nfr);
+                const ListRef XA{xs ? a.As : a.Ar, xs ? s : r, xs ? nas : nar};
+                const ListRef XF{xs ? a.Fs : a.Fr, xs ? s : r, xs ? nfs : nfr};
+                const ListRef YA{xs ? a.Ar : a.As, xs ? r : s, xs ? nar : nas};
+                const ListRef YF{xs ? a.Fr : a.Fs, xs ? r : s, xs ? nfr : nfs};
+                uint8_t v;
+                if (!cjoin<TILE>(XA, YA, ts, te, ys, ye, a.search_min, lane)) v = APRIL_TN;
+                else if (cjoin<TILE>(XA, YF, ts, te, ys, ye, a.search_min, lane) ||
+                         cjoin<TILE>(XF, YA, ts, te, ys, ye, a.search_min, lane))
+                    v = APRIL_TH;
+                else v = APRIL_INDECISIVE;
+                if (lane == 0) {
+                    a.verdict[p] = v;
+                    c_tn += v == APRIL_TN;
+                    c_th += v == APRIL_TH;
+                    c_ind += v == APRIL_INDECISIVE;
+                }
+            }
+        }
+    }
+    if (a.counts && lane == 0) {
+        if (c_tn) atomicAdd(&a.counts[0], c_tn);
+        if (c_th) atomicAdd(&a.counts[1], c_th);
+        if (c_ind) atomicAdd(&a.counts[2], c_ind);
+    }
+}
+
+__global__ void k_zero_vbyte(unsigned int *xhead, unsigned long long *counts) {
+    if (threadIdx.x < 64) xhead[threadIdx.x] = 0;
+    if (counts && threadIdx.x < 3) counts[threadIdx.x] = 0;
+}
+
+// One wave per list: decode it whole into raw start/end arrays.
+__global__ __launch_bounds__(256) void k_decode_lists(const uint8_t *bytes, const uint64_t *boff,
+                                                      const uint64_t *off, uint64_t n, uint32_t *out_s,
+                                                      uint32_t *out_e) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t waves = uint64_t(gridDim.x) * (blockDim.x / 64);
+    for (uint64_t k = uint64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6); k < n; k += waves) {
+        const uint32_t cnt = uint32_t(off[k + 1] - off[k]);
+        VCursor c = vcursor(bytes, boff[k], boff[k + 1], cnt);
+        uint32_t *s = out_s + off[k], *e = out_e + off[k];
+        while (c.g < c.nvals) {
+            const uint32_t got = vdecode_window(c, s, e, false, lane);
+            s += got;
+            e += got;
+        }
+    }
+}
+
+CList clist(const april_lists_t *L, bool f) {
+    CList c;
+    c.off = f ? L->d.off_f : L->d.off_a;
+    c.boff = f ? L->d.boff_f : L->d.boff_a;
+    c.blk = f ? L->d.blk_f : L->d.blk_a;
+    c.bytes = f ? L->d.bytes_f : L->d.bytes_a;
+    c.bval = f ? L->d.bval_f : L->d.bval_a;
+    c.bpos = f ? L->d.bpos_f : L->d.bpos_a;
+    return c;
+}
+
+}  // namespace
+
+uint64_t vbyte_workspace_bytes() { return 256; }
+
+int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
+                        uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
+                        const april_filter_opts_t &o, int cus, void *workspace, hipStream_t stream) {
+    CArgs a;
+    a.Ar = clist(R, false);
+    a.Fr = clist(R, true);
+    a.As = clist(S, false);
+    a.Fs = clist(S, true);
+    a.r = d_r;
+    a.s = d_s;
+    a.n_pairs = n_pairs;
+    a.n_r = R->n;
+    a.n_s = S->n;
+    a.verdict = d_verdict;
+    a.counts = counts;
+    a.xhead = static_cast<unsigned int *>(workspace);
+    a.xcds = uint32_t(xcd_count(cus));
+    a.search_min = o.search_min ? o.search_min : 1024;
+    k_zero_vbyte<<<1, 64, 0, stream>>>(a.xhead, counts);
+    APRIL_HIP_TRY(hipGetLastError());
+    const uint32_t tile = o.tile ? o.tile : 512;
+    const uint64_t blocks = uint64_t(cus) * 8;
+    switch (tile) {
+        case 256: k_filter_vbyte<256><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
+        case 512: k_filter_vbyte<512><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
+        case 1024: k_filter_vbyte<1024><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
+        default: return fail(APRIL_E_INVALID, "compressed lists: tile must be 256, 512 or 1024");
+    }
+    APRIL_HIP_TRY(hipGetLastError());
+    return APRIL_OK;
+}
+
+int launch_decode_lists(const april_lists_t *L, bool f, uint32_t *out_s, uint32_t *out_e, hipStream_t stream) {
+    const uint64_t n = L->n;
+    if (n == 0) return APRIL_OK;
+    const uint64_t blocks = std::min<uint64_t>((n + 3) / 4, 65535);
+    k_decode_lists<<<dim3(uint32_t(blocks)), dim3(256), 0, stream>>>(f ? L->d.bytes_f : L->d.bytes_a,
+                                                                    f ? L->d.boff_f : L->d.boff_a,
+                                                                    f ? L->d.off_f : L->d.off_a, n, out_s, out_e);
+    APRIL_HIP_TRY(hipGetLastError());
+    return APRIL_OK;
+}
+
+}  // namespace april

@@ -232,6 +232,8 @@ extern "C" int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, 
                                 void *hip_stream) {
     clear_error();
     if (int rc = check_lists(R, S)) return rc;
+    if (R->codec != APRIL_CODEC_RAW || S->codec != APRIL_CODEC_RAW)
+        return fail(APRIL_E_INVALID, "byte accounting needs raw lists");
     if (n_pairs == 0) return APRIL_OK;
     if (!d_r || !d_s || !d_bytes) return fail(APRIL_E_INVALID, "NULL pair/bytes array");
     DeviceState *st;
@@ -276,6 +278,22 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
         APRIL_HIP_TRY(hipMemcpyAsync(&bad, st->flag, sizeof(bad), hipMemcpyDeviceToHost, stream));
         APRIL_HIP_TRY(hipStreamSynchronize(stream));
         if (bad) return fail(APRIL_E_INVALID, "pair index out of range");
+    }
+    if (R->codec != S->codec) return fail(APRIL_E_INVALID, "R and S lists use different codecs");
+    if (R->codec == APRIL_CODEC_VBYTE) {
+        if (o.schedule != APRIL_SCHED_BATCHED)
+            return fail(APRIL_E_INVALID, "compressed lists need the batched schedule");
+        if (o.d_workspace) {
+            if (o.workspace_bytes < 256) return fail(APRIL_E_INVALID, "workspace too small");
+            return launch_filter_vbyte(R, S, d_r, d_s, n_pairs, d_verdict, counts, o, st->cus, o.d_workspace,
+                                       stream);
+        }
+        void *ws = nullptr;
+        hipError_t e = hipMallocAsync(&ws, 256, stream);
+        if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
+        const int rc = launch_filter_vbyte(R, S, d_r, d_s, n_pairs, d_verdict, counts, o, st->cus, ws, stream);
+        APRIL_HIP_TRY(hipFreeAsync(ws, stream));
+        return rc;
     }
     FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, d_verdict, counts);
     if (o.schedule == APRIL_SCHED_BATCHED) {

@@ -27,13 +27,33 @@ void clear_error();
     } while (0)
 
 // ------------------------------------------------------------------- lists
+// Compressed (delta + VByte) form of one list type (A or F) of a collection.
+// List k is the value sequence s_0 < e_0 < s_1 < e_1 < ...; its byte stream
+// holds varint(s_0) and then varint(v_t - v_{t-1} - 1) for t >= 1, 7 bits per
+// byte, low bits first, high bit set on every byte but a value's last.
+// Every kVbyteBlock intervals a block entry stores the absolute value of the
+// block's first start and the byte offset just after that value's varint,
+// so decoding can begin at any block.
+constexpr uint32_t kVbyteBlock = 64;
 struct DeviceArrays {
     uint64_t *off_a = nullptr, *off_f = nullptr;   // n+1 each
-    uint32_t *start_a = nullptr, *end_a = nullptr;  // n_a each
-    uint32_t *start_f = nullptr, *end_f = nullptr;  // n_f each
+    uint32_t *start_a = nullptr, *end_a = nullptr;  // n_a each (raw codec)
+    uint32_t *start_f = nullptr, *end_f = nullptr;  // n_f each (raw codec)
+    // VByte codec
+    uint64_t *boff_a = nullptr, *boff_f = nullptr;  // n+1 each: byte offsets
+    uint64_t *blk_a = nullptr, *blk_f = nullptr;    // n+1 each: first block entry
+    uint8_t *bytes_a = nullptr, *bytes_f = nullptr;
+    uint32_t *bval_a = nullptr, *bval_f = nullptr;  // per block: absolute start value
+    uint32_t *bpos_a = nullptr, *bpos_f = nullptr;  // per block: byte offset within the list
+    uint64_t n_bytes_a = 0, n_bytes_f = 0, n_blk_a = 0, n_blk_f = 0;
     void *block = nullptr;                          // one allocation holding all of the above
     size_t bytes = 0;
 };
+
+// Encode one list (n intervals) into `out` (appended); block entries into
+// bval/bpos (appended).  Returns the number of bytes written.
+uint64_t vbyte_encode(const uint32_t *s, const uint32_t *e, uint64_t n, std::vector<uint8_t> &out,
+                      std::vector<uint32_t> &bval, std::vector<uint32_t> &bpos);
 
 }  // namespace april
 
@@ -86,5 +106,24 @@ struct DeviceState {
     unsigned int *flag = nullptr;
 };
 int device_state(DeviceState **out);
+
+// One query of a served batch: its MBR and the grid cells the MBR covers.
+struct ProbeQuery {
+    double x0, y0, x1, y1;
+    uint32_t cx0, cy0, cx1, cy1;
+};
+// Candidate pairs (batch query index, S id) of a batch of queries against
+// the uniform MBR grid of S; *count receives the number found (pairs beyond
+// `cap` are not written).
+// Decode the A (f = false) or F lists of compressed device lists into raw
+// device arrays (one wavefront per list).
+int launch_decode_lists(const april_lists_t *L, bool f, uint32_t *out_s, uint32_t *out_e, hipStream_t stream);
+// The filter on compressed lists (compressed.hip); `workspace` holds 256 bytes.
+int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
+                        uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
+                        const april_filter_opts_t &o, int cus, void *workspace, hipStream_t stream);
+int launch_probe(const ProbeQuery *d_q, uint32_t n_q, const uint32_t *cell_off, const uint32_t *cell_ids,
+                 const double *boxes, const uint16_t *cells, uint32_t G, uint32_t *pr, uint32_t *ps,
+                 uint32_t cap, unsigned int *count, hipStream_t stream);
 
 }  // namespace april

@@ -106,6 +106,30 @@ void hilbert_d2xy(int order, uint64_t d, uint32_t *x, uint32_t *y) {
     *y = Y;
 }
 
+uint64_t vbyte_encode(const uint32_t *s, const uint32_t *e, uint64_t n, std::vector<uint8_t> &out,
+                      std::vector<uint32_t> &bval, std::vector<uint32_t> &bpos) {
+    const size_t base = out.size();
+    uint32_t prev = 0xffffffffu;   // so that the first value is stored as itself
+    auto put = [&](uint32_t d) {
+        while (d >= 0x80u) {
+            out.push_back(uint8_t(d | 0x80u));
+            d >>= 7;
+        }
+        out.push_back(uint8_t(d));
+    };
+    for (uint64_t i = 0; i < n; i++) {
+        put(s[i] - prev - 1u);   // first value: s_0 (prev + 1 wraps to 0)
+        prev = s[i];
+        if (i % kVbyteBlock == 0) {
+            bval.push_back(s[i]);
+            bpos.push_back(uint32_t(out.size() - base));
+        }
+        put(e[i] - prev - 1u);
+        prev = e[i];
+    }
+    return out.size() - base;
+}
+
 }  // namespace april
 
 using namespace april;
@@ -200,7 +224,7 @@ int april_lists_to_device(const april_lists_t *h, uint32_t codec, void *stream,
     clear_error();
     if (!h || !out) return fail(APRIL_E_INVALID, "NULL argument");
     if (h->device >= 0) return fail(APRIL_E_INVALID, "lists are already on a device");
-    if (codec != APRIL_CODEC_RAW) return fail(APRIL_E_INVALID, "unknown codec");
+    if (codec != APRIL_CODEC_RAW && codec != APRIL_CODEC_VBYTE) return fail(APRIL_E_INVALID, "unknown codec");
     int dev = 0;
     APRIL_HIP_TRY(hipGetDevice(&dev));
     auto *L = new (std::nothrow) april_lists;
@@ -209,13 +233,54 @@ int april_lists_to_device(const april_lists_t *h, uint32_t codec, void *stream,
     L->n = h->n; L->n_a = h->n_a; L->n_f = h->n_f;
     L->device = dev;
     L->codec = codec;
-    // one allocation: offsets first (8-byte aligned), then the four endpoint
-    // arrays, each starting on a 256-byte boundary
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
-    const size_t b_off = up(8 * (h->n + 1));
-    const size_t b_a = up(4 * std::max<uint64_t>(h->n_a, 1));
-    const size_t b_f = up(4 * std::max<uint64_t>(h->n_f, 1));
-    const size_t total = 2 * b_off + 2 * b_a + 2 * b_f;
+    const uint64_t n = h->n;
+    const size_t b_off = up(8 * (n + 1));
+    // host staging for the compressed form (kept alive in L until freed)
+    std::vector<uint64_t> boff_a, boff_f, blk_a, blk_f;
+    std::vector<uint8_t> bytes_a, bytes_f;
+    std::vector<uint32_t> bval_a, bpos_a, bval_f, bpos_f;
+    size_t total = 2 * b_off;
+    size_t b_a = 0, b_f = 0, b_ba = 0, b_bf = 0, b_va = 0, b_vf = 0;
+    if (codec == APRIL_CODEC_RAW) {
+        b_a = up(4 * std::max<uint64_t>(h->n_a, 1));
+        b_f = up(4 * std::max<uint64_t>(h->n_f, 1));
+        total += 2 * b_a + 2 * b_f;
+    } else {
+        try {
+            for (int t = 0; t < 2; t++) {
+                const auto &off = t ? h->off_f : h->off_a;
+                const auto &st = t ? h->start_f : h->start_a;
+                const auto &en = t ? h->end_f : h->end_a;
+                auto &bo = t ? boff_f : boff_a;
+                auto &bk = t ? blk_f : blk_a;
+                auto &by = t ? bytes_f : bytes_a;
+                auto &bv = t ? bval_f : bval_a;
+                auto &bp = t ? bpos_f : bpos_a;
+                bo.resize(n + 1);
+                bk.resize(n + 1);
+                by.reserve(size_t((off[n]) * 3));
+                for (uint64_t k = 0; k < n; k++) {
+                    bo[k] = by.size();
+                    bk[k] = bv.size();
+                    vbyte_encode(st.data() + off[k], en.data() + off[k], off[k + 1] - off[k], by, bv, bp);
+                }
+                bo[n] = by.size();
+                bk[n] = bv.size();
+                if (bv.size() != bp.size()) return fail(APRIL_E_INVALID, "block index mismatch");
+                // the decoder reads whole aligned 256-byte windows (+4 bytes)
+                for (uint32_t pad = 0; pad < 512; pad++) by.push_back(0);
+            }
+        } catch (...) {
+            delete L;
+            return fail(APRIL_E_NOMEM, "out of host memory");
+        }
+        b_ba = up(bytes_a.size());
+        b_bf = up(bytes_f.size());
+        b_va = up(4 * std::max<size_t>(bval_a.size(), 1));
+        b_vf = up(4 * std::max<size_t>(bval_f.size(), 1));
+        total += 4 * b_off + b_ba + b_bf + 2 * b_va + 2 * b_vf;
+    }
     hipError_t e = hipMalloc(&L->d.block, total);
     if (e != hipSuccess) {
         delete L;
@@ -224,25 +289,112 @@ int april_lists_to_device(const april_lists_t *h, uint32_t codec, void *stream,
     char *p = static_cast<char *>(L->d.block);
     L->d.off_a = reinterpret_cast<uint64_t *>(p); p += b_off;
     L->d.off_f = reinterpret_cast<uint64_t *>(p); p += b_off;
-    L->d.start_a = reinterpret_cast<uint32_t *>(p); p += b_a;
-    L->d.end_a = reinterpret_cast<uint32_t *>(p); p += b_a;
-    L->d.start_f = reinterpret_cast<uint32_t *>(p); p += b_f;
-    L->d.end_f = reinterpret_cast<uint32_t *>(p);
+    if (codec == APRIL_CODEC_RAW) {
+        L->d.start_a = reinterpret_cast<uint32_t *>(p); p += b_a;
+        L->d.end_a = reinterpret_cast<uint32_t *>(p); p += b_a;
+        L->d.start_f = reinterpret_cast<uint32_t *>(p); p += b_f;
+        L->d.end_f = reinterpret_cast<uint32_t *>(p);
+    } else {
+        L->d.boff_a = reinterpret_cast<uint64_t *>(p); p += b_off;
+        L->d.boff_f = reinterpret_cast<uint64_t *>(p); p += b_off;
+        L->d.blk_a = reinterpret_cast<uint64_t *>(p); p += b_off;
+        L->d.blk_f = reinterpret_cast<uint64_t *>(p); p += b_off;
+        L->d.bytes_a = reinterpret_cast<uint8_t *>(p); p += b_ba;
+        L->d.bytes_f = reinterpret_cast<uint8_t *>(p); p += b_bf;
+        L->d.bval_a = reinterpret_cast<uint32_t *>(p); p += b_va;
+        L->d.bpos_a = reinterpret_cast<uint32_t *>(p); p += b_va;
+        L->d.bval_f = reinterpret_cast<uint32_t *>(p); p += b_vf;
+        L->d.bpos_f = reinterpret_cast<uint32_t *>(p);
+        L->d.n_bytes_a = boff_a[n];
+        L->d.n_bytes_f = boff_f[n];
+        L->d.n_blk_a = bval_a.size();
+        L->d.n_blk_f = bval_f.size();
+    }
     L->d.bytes = total;
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto cp = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
-    hipError_t rc = cp(L->d.off_a, h->off_a.data(), 8 * (h->n + 1));
-    if (rc == hipSuccess) rc = cp(L->d.off_f, h->off_f.data(), 8 * (h->n + 1));
-    if (rc == hipSuccess) rc = cp(L->d.start_a, h->start_a.data(), 4 * h->n_a);
-    if (rc == hipSuccess) rc = cp(L->d.end_a, h->end_a.data(), 4 * h->n_a);
-    if (rc == hipSuccess) rc = cp(L->d.start_f, h->start_f.data(), 4 * h->n_f);
-    if (rc == hipSuccess) rc = cp(L->d.end_f, h->end_f.data(), 4 * h->n_f);
+    hipError_t rc = cp(L->d.off_a, h->off_a.data(), 8 * (n + 1));
+    if (rc == hipSuccess) rc = cp(L->d.off_f, h->off_f.data(), 8 * (n + 1));
+    if (codec == APRIL_CODEC_RAW) {
+        if (rc == hipSuccess) rc = cp(L->d.start_a, h->start_a.data(), 4 * h->n_a);
+        if (rc == hipSuccess) rc = cp(L->d.end_a, h->end_a.data(), 4 * h->n_a);
+        if (rc == hipSuccess) rc = cp(L->d.start_f, h->start_f.data(), 4 * h->n_f);
+        if (rc == hipSuccess) rc = cp(L->d.end_f, h->end_f.data(), 4 * h->n_f);
+    } else {
+        // the staging vectors die with this call: copy synchronously
+        if (rc == hipSuccess) rc = cp(L->d.boff_a, boff_a.data(), 8 * (n + 1));
+        if (rc == hipSuccess) rc = cp(L->d.boff_f, boff_f.data(), 8 * (n + 1));
+        if (rc == hipSuccess) rc = cp(L->d.blk_a, blk_a.data(), 8 * (n + 1));
+        if (rc == hipSuccess) rc = cp(L->d.blk_f, blk_f.data(), 8 * (n + 1));
+        if (rc == hipSuccess) rc = cp(L->d.bytes_a, bytes_a.data(), bytes_a.size());
+        if (rc == hipSuccess) rc = cp(L->d.bytes_f, bytes_f.data(), bytes_f.size());
+        if (rc == hipSuccess) rc = cp(L->d.bval_a, bval_a.data(), 4 * bval_a.size());
+        if (rc == hipSuccess) rc = cp(L->d.bpos_a, bpos_a.data(), 4 * bpos_a.size());
+        if (rc == hipSuccess) rc = cp(L->d.bval_f, bval_f.data(), 4 * bval_f.size());
+        if (rc == hipSuccess) rc = cp(L->d.bpos_f, bpos_f.data(), 4 * bpos_f.size());
+        if (rc == hipSuccess) rc = hipStreamSynchronize(s);
+    }
     if (rc != hipSuccess) {
         (void)hipFree(L->d.block);
         delete L;
         return fail(APRIL_E_HIP, std::string("upload: ") + hipGetErrorString(rc));
+    }
+    *out = L;
+    return APRIL_OK;
+}
+
+int april_lists_download(const april_lists_t *d, void *stream, april_lists_t **out) {
+    clear_error();
+    if (!d || !out) return fail(APRIL_E_INVALID, "NULL argument");
+    if (d->device < 0) return fail(APRIL_E_INVALID, "lists are not on a device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto *L = new (std::nothrow) april_lists;
+    if (!L) return fail(APRIL_E_NOMEM, "out of host memory");
+    try {
+        L->grid = d->grid;
+        L->n = d->n; L->n_a = d->n_a; L->n_f = d->n_f;
+        L->off_a.resize(d->n + 1);
+        L->off_f.resize(d->n + 1);
+        L->start_a.resize(d->n_a); L->end_a.resize(d->n_a);
+        L->start_f.resize(d->n_f); L->end_f.resize(d->n_f);
+    } catch (...) {
+        delete L;
+        return fail(APRIL_E_NOMEM, "out of host memory");
+    }
+    void *tmp = nullptr;
+    const uint32_t *sa = d->d.start_a, *ea = d->d.end_a, *sf = d->d.start_f, *ef = d->d.end_f;
+    int rc = APRIL_OK;
+    if (d->codec == APRIL_CODEC_VBYTE) {
+        const size_t na = std::max<uint64_t>(d->n_a, 1), nf = std::max<uint64_t>(d->n_f, 1);
+        if (hipMalloc(&tmp, 4 * (2 * na + 2 * nf)) != hipSuccess) {
+            delete L;
+            return fail(APRIL_E_NOMEM, "download: device scratch");
+        }
+        uint32_t *t = static_cast<uint32_t *>(tmp);
+        uint32_t *ta = t, *tea = t + na, *tf = t + 2 * na, *tef = t + 2 * na + nf;
+        rc = launch_decode_lists(d, false, ta, tea, s);
+        if (!rc) rc = launch_decode_lists(d, true, tf, tef, s);
+        sa = ta; ea = tea; sf = tf; ef = tef;
+    }
+    auto cp = [&](void *dst, const void *src, size_t b) {
+        return b ? hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, s) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    if (!rc) {
+        e = cp(L->off_a.data(), d->d.off_a, 8 * (d->n + 1));
+        if (e == hipSuccess) e = cp(L->off_f.data(), d->d.off_f, 8 * (d->n + 1));
+        if (e == hipSuccess) e = cp(L->start_a.data(), sa, 4 * d->n_a);
+        if (e == hipSuccess) e = cp(L->end_a.data(), ea, 4 * d->n_a);
+        if (e == hipSuccess) e = cp(L->start_f.data(), sf, 4 * d->n_f);
+        if (e == hipSuccess) e = cp(L->end_f.data(), ef, 4 * d->n_f);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (tmp) (void)hipFree(tmp);
+    if (rc || e != hipSuccess) {
+        delete L;
+        return rc ? rc : fail(APRIL_E_HIP, std::string("download: ") + hipGetErrorString(e));
     }
     *out = L;
     return APRIL_OK;

@@ -97,3 +97,22 @@ def skewed(k: int = 3, n: int = 200_000, n_large: int = 2000, a_large: float = 0
         out.append(PolygonSet.concat(small, big))
     R, S = out
     return R, S, grid_covering([R, S], order)
+
+
+def serving(k: int = 5, n_s: int = 1_000_000, n_queries: int = 10_000, order: int = 16):
+    """The served workload: S of n_s at-scale polygons, and a stream of query
+    polygons with 10..10^4 vertices (log-uniform), radius 5e-4..0.05
+    (log-uniform), centres from S's mixture.  Returns (S, queries, grid);
+    the grid covers S and the queries."""
+    S = scale_collection(np.random.default_rng(1000 * k + 2), n_s, k)
+    Q = query_stream(k, n_queries)
+    return S, Q, grid_covering([S, Q], order)
+
+
+def query_stream(k: int, n: int, r_range=(5e-4, 0.05), v_range=(10, 10_000)):
+    rng = np.random.default_rng(1000 * k + 3)
+    mrng = _mixture_rng(k)
+    centres = gmm_centres_shared(mrng, rng, n, SCALE_SIGMA)
+    radii = np.exp(rng.uniform(np.log(r_range[0]), np.log(r_range[1]), n))
+    nv = np.round(np.exp(rng.uniform(np.log(v_range[0]), np.log(v_range[1]), n))).astype(np.int64)
+    return star_polygons(rng, centres, radii, nv, a=0.3)

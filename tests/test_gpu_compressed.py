@@ -1,0 +1,115 @@
+"""Compressed (delta + VByte) lists, decoded while joining (Sec. 5.1).
+
+* round trip: lists uploaded compressed and decoded on the device by the
+  decoder the filter uses equal the original lists bit for bit -- lengths 0,
+  1, around the 64-interval block and 256-byte window edges, 10^5, large and
+  small gaps (1- to 5-byte varints);
+* verdicts on compressed lists equal the oracle's (random lists, the tiny
+  workload), with the block-index search forced on and off and every tile
+  size.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.intervals import ListSet, random_lists, sub_lists
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2307_01716_amd import april  # noqa: E402
+
+GRID = (0.0, 0.0, float(1 << 16) * 2.0 ** -30 * (1 << 16), 16)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def cuda(a):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).cuda()
+
+
+def collection(rng, lengths, spread):
+    A, F = [], []
+    for L, sp in zip(lengths, spread):
+        lo = int(rng.integers(0, 1 << 24))
+        a = random_lists(rng, max(L, 1), lo, min(lo + sp * max(L, 1) + 8, 2 ** 32 - 2))
+        if L == 0:
+            a = (a[0][:0], a[1][:0])
+        A.append(a)
+        F.append(sub_lists(rng, *a, p=0.6))
+    a, f = ListSet.from_lists(A), ListSet.from_lists(F)
+    return oracle.Lists(a.off, a.start, a.end, f.off, f.start, f.end)
+
+
+def upload(grid, L, codec):
+    h = april.april_lists_from_arrays(grid, L.offA, L.sA, L.eA, L.offF, L.sF, L.eF, validate=True)
+    d = april.april_lists_to_device(h, codec=codec)
+    torch.cuda.synchronize()
+    return d
+
+
+LENGTHS = [0, 1, 2, 3, 63, 64, 65, 127, 128, 129, 200, 1000, 4097, 100_000]
+
+
+@pytest.mark.parametrize("spread", [3, 200, 70_000, 30_000_000])
+def test_round_trip(spread):
+    rng = np.random.default_rng(spread)
+    lens = LENGTHS * 2
+    L = collection(rng, lens, [spread] * len(lens))
+    say(f"[vbyte] round trip spread={spread} intervals={len(L.sA)}")
+    d = upload(GRID, L, april.CODEC_VBYTE)
+    back = april.april_lists_download(d)
+    got = back.export()
+    for a, b in zip(got, (L.offA, L.sA, L.eA, L.offF, L.sF, L.eF)):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("tile,search_min", [(256, 1), (512, 1024), (1024, 64)])
+def test_random_lists_compressed(tile, search_min):
+    rng = np.random.default_rng(tile + search_min)
+    n = 160
+    lens = rng.choice([1, 5, 60, 64, 65, 130, 300, 1500, 9000], n)
+    spread = rng.choice([3, 40, 2000], n)
+    LR, LS = collection(rng, lens, spread), collection(rng, lens[::-1].copy(), spread)
+    P = 6000
+    r = rng.integers(0, n, P).astype(np.uint32)
+    s = rng.integers(0, n, P).astype(np.uint32)
+    want = oracle.filter_pairs(LR, LS, r, s)
+    say(f"[vbyte] filter tile={tile} search_min={search_min} P={P}")
+    dR, dS = upload(GRID, LR, april.CODEC_VBYTE), upload(GRID, LS, april.CODEC_VBYTE)
+    v = torch.empty(P, dtype=torch.uint8, device="cuda")
+    c = torch.empty(3, dtype=torch.int64, device="cuda")
+    april.april_filter_pairs(dR, dS, cuda(r), cuda(s), v, c, schedule=april.SCHED_BATCHED, tile=tile,
+                             search_min=search_min)
+    torch.cuda.synchronize()
+    assert np.array_equal(v.cpu().numpy(), want)
+    assert np.array_equal(c.cpu().numpy(), np.bincount(want, minlength=3))
+    assert len(set(want.tolist())) == 3
+
+
+def test_tiny_workload_compressed():
+    R, S, g = synth.configs.tiny()
+    LR, LS = oracle.build_lists(g, R), oracle.build_lists(g, S)
+    r, s = oracle.mbr_join(R, S)
+    want = oracle.filter_pairs(LR, LS, r, s)
+    hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
+    hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
+    dR = april.april_lists_to_device(hR, codec=april.CODEC_VBYTE)
+    dS = april.april_lists_to_device(hS, codec=april.CODEC_VBYTE)
+    v = torch.empty(len(r), dtype=torch.uint8, device="cuda")
+    april.april_filter_pairs(dR, dS, cuda(r), cuda(s), v, schedule=april.SCHED_BATCHED)
+    torch.cuda.synchronize()
+    assert np.array_equal(v.cpu().numpy(), want)
+    # the plain schedule refuses compressed lists
+    with pytest.raises(april.AprilError):
+        april.april_filter_pairs(dR, dS, cuda(r), cuda(s), v)

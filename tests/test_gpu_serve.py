@@ -1,0 +1,120 @@
+"""Served selection queries (Sec. 4.3.1): continuous batching on the GPU.
+
+* every result equals, bit for bit, the oracle's answer for that query: the
+  S objects whose closed MBR meets the query's, with Alg. 2's verdicts;
+* a request's result is the same alone and in a mix of concurrent requests;
+* a request larger than a slot fails with APRIL_E_NOMEM without disturbing
+  the others; cancelled requests disappear; unknown tickets are errors.
+"""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2307_01716_amd import april  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def served():
+    S, Q, g = synth.configs.serving(n_s=20_000, n_queries=300)
+    # keep the very large queries few: the mixture of sizes still spans 10..10^4
+    say(f"[serve] S={len(S)} queries={len(Q)}")
+    hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
+    dS = april.april_lists_to_device(hS)
+    torch.cuda.synchronize()
+    return S, Q, g, hS, dS
+
+
+def oracle_answer(S, g, LS, poly):
+    """(s ids ascending, verdicts) for one query, from the oracle alone."""
+    one = synth.PolygonSet(np.ascontiguousarray(poly), np.array([0, len(poly)], np.int64))
+    _, s = oracle.mbr_join(one, S)
+    LQ = oracle.build_lists(g, one)
+    v = oracle.filter_pairs(LQ, LS, np.zeros(len(s), np.uint32), s)
+    return s, v
+
+
+def test_alone_equals_mix_and_oracle(served):
+    S, Q, g, hS, dS = served
+    srv = april.Server(dS, S.mbrs(), slots=3, mem_budget=256 << 20)
+    try:
+        say("[serve] alone")
+        alone = []
+        for k in range(40):
+            t = srv.submit(Q.polygon(k))
+            r = srv.wait(t, 120)
+            alone.append(r)
+            srv.release(t)
+        say("[serve] mix")
+        tickets = [srv.submit(Q.polygon(k)) for k in range(len(Q))]
+        mix = [srv.wait(t, 300) for t in tickets]
+        for t in tickets:
+            srv.release(t)
+        for k in range(40):
+            assert np.array_equal(alone[k].s_ids, mix[k].s_ids), k
+            assert np.array_equal(alone[k].verdict, mix[k].verdict), k
+        say("[serve] oracle on a sample")
+        LS = oracle.build_lists(g, S)
+        rng = np.random.default_rng(2)
+        for k in sorted(rng.choice(len(Q), 25, replace=False)):
+            s, v = oracle_answer(S, g, LS, Q.polygon(k))
+            assert np.array_equal(mix[k].s_ids, s), k
+            assert np.array_equal(mix[k].verdict, v), k
+            assert mix[k].counts == np.bincount(v, minlength=3).tolist()
+        total = sum(len(r.s_ids) for r in mix)
+        assert total > 1000
+        lat = np.array([r.latency for r in mix])
+        assert np.all(lat > 0)
+        say(f"[serve] {total} pairs; p50 {np.median(lat) * 1e3:.1f} ms")
+    finally:
+        srv.close()
+
+
+def test_admission_limits_and_cancel(served):
+    S, Q, g, hS, dS = served
+    # a budget so small that the largest queries cannot fit one slot
+    srv = april.Server(dS, S.mbrs(), slots=2, mem_budget=2 << 20)
+    try:
+        st = srv.stats()
+        assert st["slots"] == 2 and st["cap_pairs"] >= 1024
+        tickets = [srv.submit(Q.polygon(k)) for k in range(60)]
+        ok = nomem = 0
+        for t in tickets:
+            try:
+                srv.wait(t, 120)
+                ok += 1
+            except april.AprilError as e:
+                assert e.code == april.E_NOMEM
+                nomem += 1
+            srv.release(t)
+        assert ok > 0 and nomem > 0
+        say(f"[serve] admission: {ok} served, {nomem} rejected")
+        # cancel: the ticket disappears
+        t = srv.submit(Q.polygon(0))
+        srv.cancel(t)
+        with pytest.raises(april.AprilError):
+            srv.poll(t)
+        with pytest.raises(april.AprilError):
+            srv.poll(10 ** 9)
+        # bad polygon: outside the grid
+        bad = np.array([[-5.0, -5.0], [-4.0, -5.0], [-4.0, -4.0]])
+        t = srv.submit(bad)
+        with pytest.raises(april.AprilError) as e:
+            srv.wait(t, 60)
+        assert e.value.code == april.E_GRID
+        srv.release(t)
+    finally:
+        srv.close()

@@ -71,8 +71,11 @@ extern "C" {
 typedef struct {
     double x0, y0, side;
     uint32_t order;
-    uint32_t flags;   /* reserved, must be 0 */
+    uint32_t flags;   /* 0, or APRIL_GRID_PARTITIONED in the descriptor of a
+                         partitioned collection (set by the library) */
 } april_grid_t;
+
+#define APRIL_GRID_PARTITIONED 1u
 
 /* ---------------------------------------------------------------- lists */
 /* A- and F-lists of one collection, resident on the host or on a device. */
@@ -104,6 +107,19 @@ typedef struct {
  */
 int april_build_lists(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
                       uint64_t n_polys, uint32_t flags, april_lists_t **out);
+
+/*
+ * Partitioning (Sec. 5.2): the data space is split into disjoint partitions,
+ * each with its own grid (of order <= 16) over its raster area; an object
+ * that meets several partitions has one instance per partition.  This builds
+ * one collection of instances: polygon k is rasterized on grids[grid_of[k]].
+ * The collection's descriptor is grids[0] with APRIL_GRID_PARTITIONED set,
+ * and the filter accepts R and S only if they were built on the same set of
+ * grids; the caller pairs only instances of the same partition.
+ */
+int april_build_lists_partitioned(const april_grid_t *grids, uint32_t n_grids, const uint32_t *grid_of,
+                                  const double *xy, const uint64_t *vtx_off, uint64_t n_polys,
+                                  uint32_t flags, april_lists_t **out);
 
 /*
  * Wrap caller-made lists (host arrays, copied) as host lists on `grid`.

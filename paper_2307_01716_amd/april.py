@@ -21,6 +21,7 @@ OK, PENDING = 0, 1
 E_INVALID, E_GRID, E_NOMEM, E_HIP, E_CORRUPT, E_NODEV = -1, -2, -3, -4, -5, -6
 TN, TH, INDECISIVE, BAD_PAIR = 0, 1, 2, 255
 STRICT = 1
+GRID_PARTITIONED = 1
 CODEC_RAW, CODEC_VBYTE = 0, 1
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 VALIDATE = 1
@@ -98,6 +99,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     P, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
     L.april_build_lists.argtypes = [C.POINTER(april_grid_t), P, P, u64, u32, C.POINTER(P)]
+    L.april_build_lists_partitioned.argtypes = [P, u32, P, P, P, u64, u32, C.POINTER(P)]
     L.april_lists_from_arrays.argtypes = [C.POINTER(april_grid_t), u64, P, P, P, P, P, P, i32,
                                           C.POINTER(P)]
     L.april_lists_info.argtypes = [P, C.POINTER(april_lists_info_t)]
@@ -121,7 +123,7 @@ def lib():
     L.april_serve_destroy.argtypes = [P]
     L.april_serve_destroy.restype = None
     L.april_last_error.restype = C.c_char_p
-    for name in ("april_build_lists", "april_lists_from_arrays", "april_lists_info",
+    for name in ("april_build_lists", "april_build_lists_partitioned", "april_lists_from_arrays", "april_lists_info",
                  "april_lists_export", "april_lists_to_device", "april_lists_download",
                  "april_filter_pairs",
                  "april_alg2_bytes", "april_filter_workspace_size",

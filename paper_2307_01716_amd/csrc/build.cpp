@@ -52,6 +52,7 @@ struct Result {
 class Builder {
 public:
     Builder(const LatticeGrid &g) : g_(g) {}
+    void set_grid(const LatticeGrid &g) { g_ = g; }
 
     int run(const Poly &p, Result &out);
 
@@ -61,7 +62,7 @@ private:
     bool centre_inside(uint32_t i, uint32_t j) const;
     void push_f(uint64_t s, uint64_t e, std::vector<uint32_t> &f);
 
-    const LatticeGrid g_;
+    LatticeGrid g_;
     std::vector<uint64_t> touched_;          // (hilbert id << 1) | interior crossed
     int64_t jmin_ = 0, jmax_ = 0;
     std::vector<uint32_t> row_off_;          // CSR of crossings per row
@@ -217,14 +218,13 @@ int Builder::run(const Poly &p, Result &out) {
 
 using namespace april;
 
-extern "C" int april_build_lists(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
-                                 uint64_t n, uint32_t flags, april_lists_t **out) {
-    clear_error();
-    if (!grid || !xy || !vtx_off || !out) return fail(APRIL_E_INVALID, "NULL argument");
-    if (n == 0) return fail(APRIL_E_INVALID, "no polygons");
-    if (flags & ~APRIL_STRICT) return fail(APRIL_E_INVALID, "unknown flags");
-    LatticeGrid g;
-    if (int rc = lattice_grid(grid, &g)) return rc;
+namespace {
+
+// Build every polygon k on grid lg[gid(k)]; one collection out.
+template <class GridOf>
+int build_collection(const std::vector<LatticeGrid> &lg, GridOf gid, const april_grid_t &desc,
+                     uint64_t key, const double *xy, const uint64_t *vtx_off, uint64_t n, uint32_t flags,
+                     april_lists_t **out) {
     for (uint64_t k = 0; k < n; k++)
         if (vtx_off[k + 1] < vtx_off[k] + 3) return fail(APRIL_E_INVALID, "polygon with < 3 vertices");
     const bool strict = flags & APRIL_STRICT;
@@ -233,11 +233,13 @@ extern "C" int april_build_lists(const april_grid_t *grid, const double *xy, con
     std::atomic<int> err{0};
     const int T = int(std::min<uint64_t>(host_threads(), n));
     parallel(T, [&](int) {
-        Builder b(g);
+        Builder b(lg[0]);
         Poly p;
         for (;;) {
             const uint64_t k = next.fetch_add(1);
             if (k >= n || err.load()) break;
+            const LatticeGrid &g = lg[gid(k)];
+            b.set_grid(g);
             const uint64_t v0 = vtx_off[k], v1 = vtx_off[k + 1];
             p.x.clear();
             p.y.clear();
@@ -285,7 +287,8 @@ extern "C" int april_build_lists(const april_grid_t *grid, const double *xy, con
     auto *L = new (std::nothrow) april_lists;
     if (!L) return fail(APRIL_E_NOMEM, "out of host memory");
     try {
-        L->grid = *grid;
+        L->grid = desc;
+        L->partition_key = key;
         L->n = n;
         L->off_a.resize(n + 1);
         L->off_f.resize(n + 1);
@@ -329,4 +332,41 @@ extern "C" int april_build_lists(const april_grid_t *grid, const double *xy, con
     }
     *out = L;
     return APRIL_OK;
+}
+
+}  // namespace
+
+extern "C" int april_build_lists(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
+                                 uint64_t n, uint32_t flags, april_lists_t **out) {
+    clear_error();
+    if (!grid || !xy || !vtx_off || !out) return fail(APRIL_E_INVALID, "NULL argument");
+    if (n == 0) return fail(APRIL_E_INVALID, "no polygons");
+    if (flags & ~APRIL_STRICT) return fail(APRIL_E_INVALID, "unknown flags");
+    std::vector<LatticeGrid> lg(1);
+    if (int rc = lattice_grid(grid, &lg[0])) return rc;
+    return build_collection(lg, [](uint64_t) { return 0u; }, *grid, 0, xy, vtx_off, n, flags, out);
+}
+
+extern "C" int april_build_lists_partitioned(const april_grid_t *grids, uint32_t n_grids,
+                                             const uint32_t *grid_of, const double *xy,
+                                             const uint64_t *vtx_off, uint64_t n, uint32_t flags,
+                                             april_lists_t **out) {
+    clear_error();
+    if (!grids || !grid_of || !xy || !vtx_off || !out || n_grids == 0)
+        return fail(APRIL_E_INVALID, "NULL argument");
+    if (n == 0) return fail(APRIL_E_INVALID, "no polygons");
+    if (flags & ~APRIL_STRICT) return fail(APRIL_E_INVALID, "unknown flags");
+    std::vector<LatticeGrid> lg(n_grids);
+    uint64_t key = 1469598103934665603ull;   // FNV-1a over the grid descriptors
+    for (uint32_t t = 0; t < n_grids; t++) {
+        if (int rc = lattice_grid(&grids[t], &lg[t])) return rc;
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(&grids[t]);
+        for (size_t u = 0; u < sizeof(april_grid_t); u++) key = (key ^ b[u]) * 1099511628211ull;
+    }
+    for (uint64_t k = 0; k < n; k++)
+        if (grid_of[k] >= n_grids) return fail(APRIL_E_INVALID, "grid index out of range");
+    april_grid_t desc = grids[0];
+    desc.flags = APRIL_GRID_PARTITIONED;
+    return build_collection(lg, [&](uint64_t k) { return grid_of[k]; }, desc, key, xy, vtx_off, n, flags,
+                            out);
 }

@@ -202,7 +202,8 @@ static int check_lists(const april_lists_t *R, const april_lists_t *S) {
     if (!R || !S) return fail(APRIL_E_INVALID, "NULL lists");
     if (R->device < 0 || S->device < 0) return fail(APRIL_E_INVALID, "lists must be on a device");
     if (R->device != S->device) return fail(APRIL_E_INVALID, "lists on different devices");
-    if (!same_grid(R->grid, S->grid)) return fail(APRIL_E_GRID, "R and S lists use different grids");
+    if (!same_grid(R->grid, S->grid) || R->partition_key != S->partition_key)
+        return fail(APRIL_E_GRID, "R and S lists use different grids");
     int cur = 0;
     APRIL_HIP_TRY(hipGetDevice(&cur));
     if (cur != R->device) return fail(APRIL_E_INVALID, "current device does not hold the lists");

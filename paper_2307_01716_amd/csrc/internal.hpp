@@ -59,6 +59,7 @@ uint64_t vbyte_encode(const uint32_t *s, const uint32_t *e, uint64_t n, std::vec
 
 struct april_lists {
     april_grid_t grid{};
+    uint64_t partition_key = 0;      // partitioned collections: hash of all partition grids
     uint64_t n = 0, n_a = 0, n_f = 0;
     int device = -1;                 // -1: host lists
     uint32_t codec = APRIL_CODEC_RAW;

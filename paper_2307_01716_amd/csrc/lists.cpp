@@ -27,13 +27,13 @@ int host_threads() {
 }
 
 bool same_grid(const april_grid_t &a, const april_grid_t &b) {
-    return a.x0 == b.x0 && a.y0 == b.y0 && a.side == b.side && a.order == b.order;
+    return a.x0 == b.x0 && a.y0 == b.y0 && a.side == b.side && a.order == b.order && a.flags == b.flags;
 }
 
 int lattice_grid(const april_grid_t *g, LatticeGrid *out) {
     if (!g) return fail(APRIL_E_INVALID, "grid is NULL");
     if (g->order < 1 || g->order > 16) return fail(APRIL_E_GRID, "grid order must be 1..16");
-    if (g->flags) return fail(APRIL_E_INVALID, "grid flags must be 0");
+    if (g->flags & ~APRIL_GRID_PARTITIONED) return fail(APRIL_E_INVALID, "unknown grid flags");
     const double sl = g->side * 1073741824.0;
     const int64_t cells = int64_t(1) << g->order;
     if (!(sl >= cells) || sl > 9.0e15) return fail(APRIL_E_GRID, "grid side out of range");
@@ -230,6 +230,7 @@ int april_lists_to_device(const april_lists_t *h, uint32_t codec, void *stream,
     auto *L = new (std::nothrow) april_lists;
     if (!L) return fail(APRIL_E_NOMEM, "out of host memory");
     L->grid = h->grid;
+    L->partition_key = h->partition_key;
     L->n = h->n; L->n_a = h->n_a; L->n_f = h->n_f;
     L->device = dev;
     L->codec = codec;
@@ -354,6 +355,7 @@ int april_lists_download(const april_lists_t *d, void *stream, april_lists_t **o
     if (!L) return fail(APRIL_E_NOMEM, "out of host memory");
     try {
         L->grid = d->grid;
+        L->partition_key = d->partition_key;
         L->n = d->n; L->n_a = d->n_a; L->n_f = d->n_f;
         L->off_a.resize(d->n + 1);
         L->off_f.resize(d->n + 1);

@@ -116,3 +116,12 @@ def query_stream(k: int, n: int, r_range=(5e-4, 0.05), v_range=(10, 10_000)):
     radii = np.exp(rng.uniform(np.log(r_range[0]), np.log(r_range[1]), n))
     nv = np.round(np.exp(rng.uniform(np.log(v_range[0]), np.log(v_range[1]), n))).astype(np.int64)
     return star_polygons(rng, centres, radii, nv, a=0.3)
+
+
+def partitioned(k: int = 4, n: int = 500_000, parts: int = 16, order: int = 16):
+    """The partitioned workload: two at-scale collections of n polygons, the
+    unit square cut into parts x parts partitions with a grid of `order` each."""
+    from .partitions import layout
+    R = scale_collection(np.random.default_rng(1000 * k + 1), n, k)
+    S = scale_collection(np.random.default_rng(1000 * k + 2), n, k)
+    return R, S, layout(R, S, parts, order)

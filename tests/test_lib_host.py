@@ -181,3 +181,29 @@ def test_filter_rejects_host_lists():
     with pytest.raises(april.AprilError) as e:
         april.april_filter_pairs(L, L, 0, 0, 0, None, stream=0)
     assert e.value.code == april.E_INVALID
+
+
+def test_partitioned_build_and_pairs_match_oracle():
+    from paper_2307_01716_amd import partitioned
+    R, S, g = synth.configs.tiny(n=400)
+    lay = synth.partitions.layout(R, S, 4, 10)
+    hR = partitioned.build_instances(lay, R, "r")
+    hS = partitioned.build_instances(lay, S, "s")
+    # every instance's lists equal the oracle's on its partition's grid
+    offA, sA, eA, offF, sF, eF = hR.export()
+    part = lay.r_part()
+    for p in range(16):
+        a, b = int(lay.r_off[p]), int(lay.r_off[p + 1])
+        if a == b:
+            continue
+        O = oracle.build_lists(lay.grids[p], R.subset(lay.r_obj[a:b]))
+        assert np.array_equal(offA[a:b + 1] - offA[a], O.offA)
+        assert np.array_equal(sA[offA[a]:offA[b]], O.sA)
+        assert np.array_equal(eF[offF[a]:offF[b]], O.eF)
+    assert np.all(part[:-1] <= part[1:])
+    r, s = partitioned.pairs(lay, R, S)
+    rg, sg = lay.r_obj[r], lay.s_obj[s]
+    k = np.lexsort((sg, rg))
+    ro, so = oracle.mbr_join(R, S)
+    assert np.array_equal(rg[k], ro) and np.array_equal(sg[k], so)
+    assert hR.info().n_objects == len(lay.r_obj)

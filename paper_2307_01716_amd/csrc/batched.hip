@@ -501,9 +501,12 @@ constexpr uint64_t kCtrBytes = 256;
 
 template <int TILE, int C>
 int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
-    int per_cu = 0;
-    APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<TILE, C>, kBlock, 0));
-    if (per_cu < 1) per_cu = 1;
+    static int per_cu = 0;   // resident workgroups per CU (same on every gfx950 device)
+    if (!per_cu) {
+        int q = 0;
+        APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_batched<TILE, C>, kBlock, 0));
+        per_cu = q < 1 ? 1 : q;
+    }
     uint64_t blocks = uint64_t(cus) * per_cu;
     if (waves) blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
     k_batched<TILE, C><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(b);

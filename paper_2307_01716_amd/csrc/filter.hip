@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -178,9 +179,11 @@ __global__ void k_check_pairs(const uint32_t *r, const uint32_t *s, uint64_t n, 
 
 int device_state(DeviceState **out) {
     static DeviceState states[64];
+    static std::mutex mu;
     int dev = 0;
     APRIL_HIP_TRY(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(APRIL_E_NODEV, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(mu);
     DeviceState &st = states[dev];
     if (!st.cus) {
         hipDeviceProp_t p;

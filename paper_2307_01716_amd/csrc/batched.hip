@@ -532,8 +532,8 @@ int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? cus / 32 : 1; }
 
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
                    hipStream_t stream) {
-    const uint32_t tile = o.tile ? o.tile : 256;
-    const uint32_t chunk = o.chunk ? o.chunk : 2;
+    const uint32_t tile = o.tile ? o.tile : 512;
+    const uint32_t chunk = o.chunk ? o.chunk : 1;
     BatchArgs b;
     b.f = a;
     char *ws = static_cast<char *>(workspace);
@@ -544,7 +544,7 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     b.queue[Q_THREAD] = b.queue[Q_WAVE] = nullptr;
     b.queue[Q_BLOCK] = reinterpret_cast<uint32_t *>(ws + kCtrBytes);
     b.thread_max = o.thread_max ? o.thread_max : 8;
-    b.search_min = o.search_min ? o.search_min : 1024;
+    b.search_min = o.search_min ? o.search_min : 512;
     b.grab = 64;
     if (b.thread_max >= tile) return fail(APRIL_E_INVALID, "thread_max must be below tile");
     k_zero_batch<<<1, 64, 0, stream>>>(b.tail, a.counts);

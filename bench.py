@@ -185,16 +185,17 @@ def main():
     if args.schedule in ("both", "batched"):
         from paper_2307_01716_amd import tune
         ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
-        cfg = {}
+        cfg, kw = {}, {}
         if not args.no_tune:
             t0 = time.time()
-            cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3)
+            cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3, log=log)
             log(f"autotune: {len(table)} settings in {time.time() - t0:.1f}s; best {cfg} "
                 f"({best_ms:.3f} ms)")
+            kw = tune.call_config(cfg)
 
         def batched_eager():
             april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_BATCHED,
-                                     workspace=ws, stream=stream, **cfg)
+                                     workspace=ws, stream=stream, **kw)
 
         if args.no_graph:
             fn = batched_eager
@@ -208,7 +209,7 @@ def main():
                 with torch.cuda.graph(graph, stream=cap):
                     april.april_filter_pairs(dR, dS, r, s, verdict, counts,
                                              schedule=april.SCHED_BATCHED, workspace=ws,
-                                             stream=torch.cuda.current_stream(), **cfg)
+                                             stream=torch.cuda.current_stream(), **kw)
             torch.cuda.synchronize()
             fn = graph.replay
         forms["batched"] = form("batched", *timed(fn, args.steps, args.warmup))

@@ -7,32 +7,47 @@
 //     some X_i overlaps Y_j   <=>   i*(j) exists and X_{i*(j)}.start < Y_j.end.
 // (<=: the pair is an overlap.  =>: an overlapping X_i has X_i.end >
 // Y_j.start, so i*(j) <= i and X_{i*(j)}.start <= X_i.start < Y_j.end.)
-// So one list X is kept in LDS and every lane takes elements of the other
-// list Y, read in coalesced chunks, and binary-searches X for i*(j); a
-// ballot gives the join's result after each chunk (early exit).  Elements of
-// Y that end before X starts or start after X ends cannot overlap; long
-// streamed lists are first cut to that window by a 64-ary search.  When X is
-// longer than LDS it is processed tile by tile; an overlap (X_i, Y_j) is
-// found in the tile holding X_i, because Y_j lies in that tile's window.
+// So one object's lists X are kept in LDS and every lane takes an element of
+// the other object's list Y, read in coalesced chunks, and binary-searches X
+// for i*(j); a ballot gives the join's result after each chunk (early exit).
+// Elements of Y that end before X starts or start after X ends cannot
+// overlap; long streamed lists are first cut to that window by a 64-ary
+// search.
 //
 // The three joins of Alg. 2 (AA, AF = A(r) x F(s), FA = F(r) x A(s)) are
-// symmetric in r and s, so the LDS side can be either object: with X the
-// resident object and Y the streamed one, the joins are X.A x Y.A, then
-// X.A x Y.F and X.F x Y.A.  The verdict is Alg. 2's: no AA overlap -> true
+// symmetric in r and s, so the LDS side can be either object.  With X the
+// resident object and Y the streamed one, one pass over Y.A gives AA and,
+// since every F interval lies inside an A interval, FA as well: an X.F
+// interval that overlaps Y_j lies in an X.A interval that overlaps Y_j, so
+// X.F needs to be searched only for the Y.A elements that hit X.A.  A second
+// pass over Y.F gives AF.  The verdict is Alg. 2's: no AA overlap -> true
 // negative; else an overlap in either of the other two -> true hit; else
 // indecisive.
 //
-// Bins (chosen per pair by the binning kernel):
-//   THREAD  all four lists short: one lane runs Alg. 2 sequentially;
-//   WAVE    one side's A- and F-lists fit the per-wave LDS tile: that side
-//           is resident (reused by consecutive pairs on the same object),
-//           the other streamed, one wavefront per pair;
-//   BLOCK   both sides longer: the shorter side is resident in the whole
-//           workgroup's LDS, tile by tile, and the four wavefronts stream
-//           the other side's window together.
-// The persistent kernel drains BLOCK, then WAVE, then THREAD (largest work
-// first); queues are filled once per call, so every wave exits when they
-// are empty.
+// LDS layout and search.  A wave's resident lists are four arrays of TILE
+// words (A.start, A.end, F.start, F.end).  Slots from the list's length up
+// to the next power of two hold 0xFFFFFFFF, which is never at or below a
+// start value (starts are below 2^32 - 1), so the search for i*(j) is a
+// fixed sequence of compare-and-step rounds with no bounds tests, and the
+// slot it lands on past the list's end holds a start that overlaps nothing.
+//
+// Lists longer than a tile.  X is cut into pieces by Hilbert key: piece k
+// covers keys [k_k, k_{k+1}) and holds every X.A and X.F element that meets
+// that range (at most TILE - 1 of each); the streamed Y elements are those
+// that meet it.  An overlap at key p is found in the piece whose range holds
+// p, because both elements meet that range; the F-inside-A argument above
+// holds per piece for the same reason.
+//
+// Work distribution: one persistent kernel, every pair handled by one wave,
+// in input order (pairs close in the input share lists, and the library's
+// MBR join emits them grouped by R object).  Each XCD drains its own
+// contiguous range of the input (so those lists meet in that XCD's L2),
+// then helps the others.  A wave takes `grab` pairs at a time, one lane per
+// pair's metadata, and fewer once the range is nearly drained so that waves
+// finish together.  The object whose lists fit a tile is resident (R when
+// both do, kept while consecutive pairs share it); when neither fits, the
+// one with the shorter lists is resident piece by piece.  Pairs whose four
+// lists are all very short run Alg. 2 sequentially, one lane per pair.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,80 +58,37 @@
 namespace april {
 namespace {
 
-constexpr uint32_t kSideS = 0x80000000u;   // queue entry: resident side is S
-enum { Q_THREAD = 0, Q_WAVE = 1, Q_BLOCK = 2 };
+constexpr uint32_t kSideS = 0x80000000u;   // resident-object key: the object is from S
+constexpr uint32_t kNone = 0xffffffffu;    // no resident object / no upper key bound
 
 struct BatchArgs {
     FilterArgs f;
-    uint32_t *queue[3];          // pair index | kSideS (only the workgroup queue is used)
-    unsigned int *tail;          // [3] entries per queue (binning kernel)
-    unsigned int *head;          // [3] entries taken (persistent kernel)
     unsigned int *xhead;         // [xcds] pairs taken from each XCD's range
     uint32_t xcds;
     uint32_t thread_max;
     uint32_t search_min;
-    uint32_t grab;
+    uint32_t grab;               // pairs per grab (<= 64)
+    uint32_t tail_grab;          // pairs per grab near a range's end
+    uint64_t tail_pairs;         // "near the end": fewer pairs than this left
 };
-
-// rank of this lane among the set lanes of `mask` below it
-__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-}
 
 // ---------------------------------------------------------------- binning
 
-__global__ __launch_bounds__(256) void k_zero_batch(unsigned int *ctr, unsigned long long *counts) {
+__global__ __launch_bounds__(64) void k_zero_batch(unsigned int *ctr, unsigned long long *counts) {
     if (threadIdx.x < 64) ctr[threadIdx.x] = 0;
     if (counts && threadIdx.x < 3) counts[threadIdx.x] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_bin(BatchArgs b, uint32_t tile) {
-    const FilterArgs &a = b.f;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-    for (uint64_t base = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); base < a.n_pairs;
-         base += stride) {
-        const uint64_t p = base + lane;
-        bool big = false;
-        uint32_t entry = uint32_t(p);
-        if (p < a.n_pairs) {
-            const uint32_t r = a.r[p], s = a.s[p];
-            if (r >= a.n_r || s >= a.n_s) {
-                a.verdict[p] = APRIL_BAD_PAIR;
-            } else {
-                const uint64_t nar = a.Ar.off[r + 1] - a.Ar.off[r], nfr = a.Fr.off[r + 1] - a.Fr.off[r];
-                const uint64_t nas = a.As.off[s + 1] - a.As.off[s], nfs = a.Fs.off[s + 1] - a.Fs.off[s];
-                const uint64_t mr = nar > nfr ? nar : nfr, ms = nas > nfs ? nas : nfs;
-                // neither side fits a wavefront's LDS: workgroup queue, the
-                // shorter side resident
-                if ((mr > ms ? mr : ms) > b.thread_max && mr > tile && ms > tile) {
-                    big = true;
-                    if (ms < mr) entry |= kSideS;
-                }
-            }
-        }
-        const uint64_t mask = __ballot(big);
-        if (mask) {
-            const uint32_t leader = __builtin_ctzll(mask);
-            unsigned int pos = 0;
-            if (lane == leader) pos = atomicAdd(&b.tail[Q_BLOCK], unsigned(__popcll(mask)));
-            pos = __shfl(pos, leader);
-            if (big) b.queue[Q_BLOCK][pos + rank_in(mask)] = entry;
-        }
-    }
-}
-
 // ------------------------------------------------------------ join pieces
 
-// first j in [0, m) with ye[j] > key (m if none): wave-cooperative 64-ary
-// search, one global round trip per factor of 64
-__device__ uint32_t wave_first_end_after(const uint32_t *__restrict__ ye, uint32_t m, uint32_t key,
-                                         uint32_t lane) {
+// first j in [0, m) with v[j] > key (m if none), v sorted: wave-cooperative
+// 64-ary search, one global round trip per factor of 64
+__device__ uint32_t wave_first_above(const uint32_t *__restrict__ v, uint32_t m, uint32_t key, uint32_t lane) {
     uint32_t lo = 0, hi = m;
     while (hi - lo > 64) {
         const uint64_t step = (uint64_t(hi - lo) + 63) >> 6;
         const uint64_t probe = lo + (lane + 1) * step - 1;
-        const bool pred = probe >= hi ? true : (ye[probe] > key);
+        const bool pred = probe >= hi ? true : (v[probe] > key);
         const uint64_t mask = __ballot(pred);
         if (!mask) { lo = hi; break; }
         const uint64_t f = __builtin_ctzll(mask);
@@ -127,162 +99,156 @@ __device__ uint32_t wave_first_end_after(const uint32_t *__restrict__ ye, uint32
     }
     if (hi - lo == 0) return lo;
     const uint32_t j = lo + lane;
-    const bool pred = j >= hi ? true : (ye[j] > key);
+    const bool pred = j >= hi ? true : (v[j] > key);
     const uint64_t mask = __ballot(pred);
     return mask ? lo + uint32_t(__builtin_ctzll(mask)) : hi;
 }
 
-// For C streamed elements per lane: does Y[j] overlap the resident list X
-// (n entries in LDS, sorted)?  Branch-free lower bound on X.end.
-template <int C>
-__device__ __forceinline__ bool probe_resident(const uint2 *X, uint32_t n, const uint32_t (&ys)[C],
-                                               const uint32_t (&ye)[C], const bool (&valid)[C]) {
-    uint32_t pos[C];
-#pragma unroll
-    for (int c = 0; c < C; c++) pos[c] = 0;
-    for (uint32_t step = 1u << (31 - __builtin_clz(n)); step; step >>= 1) {
-#pragma unroll
-        for (int c = 0; c < C; c++) {
-            const uint32_t q = pos[c] + step;
-            if (q <= n && X[q - 1].y <= ys[c]) pos[c] = q;
-        }
-    }
-    bool hit = false;
-#pragma unroll
-    for (int c = 0; c < C; c++) hit |= valid[c] && pos[c] < n && X[pos[c]].x < ye[c];
-    return hit;
-}
-
-// Stream Y[j_begin..) against X (LDS, n > 0) until an overlap is seen, Y is
-// exhausted, or Y starts at/after x_hi.  `stride`/`first` let several waves
-// share one Y window (chunk k of this wave is first + k * stride chunks).
-template <int C>
-__device__ __forceinline__ bool stream_overlap(const uint2 *X, uint32_t n, uint32_t x_hi,
-                               const uint32_t *__restrict__ ys, const uint32_t *__restrict__ ye,
-                               uint32_t m, uint32_t j_begin, uint32_t first, uint32_t stride,
-                               uint32_t lane, const volatile int *stop) {
-    constexpr uint32_t CH = 64 * C;
-    for (uint32_t base = j_begin + first * CH; base < m; base += stride * CH) {
-        if (stop && *stop) return false;
-        uint32_t s[C], e[C];
-        bool valid[C];
-#pragma unroll
-        for (int c = 0; c < C; c++) {
-            const uint32_t j = base + c * 64 + lane;
-            valid[c] = j < m;
-            s[c] = valid[c] ? ys[j] : 0xffffffffu;
-            e[c] = valid[c] ? ye[j] : 0u;
-        }
-        if (__any(probe_resident<C>(X, n, s, e, valid))) return true;
-        // the chunk's first element already starts at or after X's end
-        if (uniform(__shfl(s[0], 0)) >= x_hi) return false;
-    }
-    return false;
-}
-
-// X resident in this wave's LDS (n entries), Y global (m entries).
-template <int C>
-__device__ __forceinline__ bool wave_overlap(const uint2 *X, uint32_t n, const uint32_t *__restrict__ ys,
-                             const uint32_t *__restrict__ ye, uint32_t m, uint32_t search_min,
-                             uint32_t lane) {
-    if (n == 0 || m == 0) return false;
-    const uint32_t x_lo = X[0].x, x_hi = X[n - 1].y;
-    const uint32_t j0 = m > search_min ? wave_first_end_after(ye, m, x_lo, lane) : 0;
-    return stream_overlap<C>(X, n, x_hi, ys, ye, m, j0, 0, 1, lane, nullptr);
-}
-
-struct Side {
-    uint64_t a0, na, f0, nf;
-};
-
-__device__ __forceinline__ Side side_of(const ListView &A, const ListView &F, uint32_t o) {
-    Side s;
-    s.a0 = A.off[o];
-    s.na = A.off[o + 1] - s.a0;
-    s.f0 = F.off[o];
-    s.nf = F.off[o + 1] - s.f0;
-    return s;
-}
-
-// wave-cooperative copy of n intervals into LDS
-__device__ __forceinline__ void load_resident(uint2 *dst, const uint32_t *__restrict__ s,
-                                              const uint32_t *__restrict__ e, uint32_t n,
-                                              uint32_t lane, uint32_t width) {
-    for (uint32_t t = lane; t < n; t += width) dst[t] = make_uint2(s[t], e[t]);
-}
-
-// ------------------------------------------------------------- persistent
-
-// first i in [0, n) with E[i] > key (n if none), E sorted, in LDS
-__device__ __forceinline__ uint32_t first_end_after(const uint32_t *E, uint32_t n, uint32_t key) {
-    uint32_t pos = 0;
-    for (uint32_t step = n ? 1u << (31 - __builtin_clz(n)) : 0u; step; step >>= 1) {
-        const uint32_t q = pos + step;
-        if (q <= n && E[q - 1] <= key) pos = q;
-    }
-    return pos;
-}
-
-// Resident lists of one wave, SoA in LDS: A.start, A.end, F.start, F.end.
+// Resident lists of one wave (SoA in LDS, sentinel-padded) and their search
+// depths: 2^depth is the smallest power of two above the length.
 struct Resident {
     uint32_t *as, *ae, *fs, *fe;
-    uint32_t na, nf;
+    uint32_t na, nf, da, df;
 };
 
-// Join of the resident list (RS, RE, n) with the streamed list Y: true iff
-// some Y element overlaps some resident element.  With `fs`/`fe` set, Y is
-// an A-list and every Y element that overlaps the resident A-list is also
-// tested against the resident F-list; *th reports an F overlap (then the
-// loop stops: the pair is a true hit).
-template <int C>
-__device__ __forceinline__ bool stream_join_resident(const uint32_t *RS, const uint32_t *RE, uint32_t n,
-                                                     const uint32_t *FS, const uint32_t *FE, uint32_t nf,
-                                                     const uint32_t *__restrict__ ys,
-                                                     const uint32_t *__restrict__ ye, uint32_t m,
-                                                     uint32_t search_min, uint32_t lane, bool *th) {
-    if (n == 0 || m == 0) return false;
-    const uint32_t x_lo = RS[0], x_hi = RE[n - 1];
-    uint32_t j = m > search_min ? wave_first_end_after(ye, m, x_lo, lane) : 0;
-    bool any_hit = false;
+__device__ __forceinline__ uint32_t depth_of(uint32_t n) { return 32u - __clz(n); }
+
+// number of entries <= key in E (first i with E[i] > key); E holds a sorted
+// list padded with 0xFFFFFFFF to 2^depth entries, depth <= log2(TILE)
+template <int TILE>
+__device__ __forceinline__ uint32_t lds_rank(const uint32_t *E, uint32_t depth, uint32_t key) {
+    const uint32_t *p = E;   // stepping the address keeps each round to one add
+#pragma unroll
+    for (uint32_t S = TILE / 2; S > 0; S >>= 1) {
+        if (S < (1u << depth)) p = p[S - 1] <= key ? p + S : p;
+    }
+    return uint32_t(p - E);
+}
+
+// copy n < TILE intervals into a resident pair of arrays and pad them
+__device__ __forceinline__ void load_list(uint32_t *S, uint32_t *E, const uint32_t *__restrict__ gs,
+                                          const uint32_t *__restrict__ ge, uint32_t n, uint32_t lane) {
+    const uint32_t P = 1u << depth_of(n);
+    for (uint32_t t = lane; t < P; t += 64) {
+        const bool v = t < n;
+        S[t] = v ? gs[t] : 0xffffffffu;
+        E[t] = v ? ge[t] : 0xffffffffu;
+    }
+}
+
+// Stream Y[j..m) (sorted, disjoint) against the resident A-list until an
+// element starts at or after `stop`; true iff some element overlaps it.  With
+// FA, each element that overlaps the A-list is also tested against the
+// resident F-list, and an overlap there sets *th and ends the scan.
+template <int TILE, int C, bool FA>
+__device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *__restrict__ ys,
+                                             const uint32_t *__restrict__ ye, uint32_t j, uint32_t m,
+                                             uint32_t stop, uint32_t lane, bool *th) {
+    bool any = false;
     for (; j < m; j += 64 * C) {
         uint32_t s[C], e[C];
 #pragma unroll
         for (int c = 0; c < C; c++) {
             const uint32_t k = j + c * 64 + lane;
             const bool v = k < m;
-            s[c] = v ? ys[k] : 0xffffffffu;
+            s[c] = v ? ys[k] : 0u;   // idle lanes: an empty [0, 0) element
             e[c] = v ? ye[k] : 0u;
         }
-        uint32_t pos[C];
-#pragma unroll
-        for (int c = 0; c < C; c++) pos[c] = 0;
-        for (uint32_t step = 1u << (31 - __builtin_clz(n)); step; step >>= 1) {
-#pragma unroll
-            for (int c = 0; c < C; c++) {
-                const uint32_t q = pos[c] + step;
-                if (q <= n && RE[q - 1] <= s[c]) pos[c] = q;
-            }
-        }
-        bool hit = false, fhit = false;
+        // this chunk and all later ones start at or after the piece's end
+        if (uniform(s[0]) >= stop) break;
+        bool h[C];
+        bool hit = false;
 #pragma unroll
         for (int c = 0; c < C; c++) {
-            const bool h = pos[c] < n && RS[pos[c]] < e[c];
-            hit |= h;
-            if (FS && h) {
-                const uint32_t pf = first_end_after(FE, nf, s[c]);
-                fhit |= pf < nf && FS[pf] < e[c];
+            const uint32_t pos = lds_rank<TILE>(x.ae, x.da, s[c]);
+            h[c] = x.as[pos] < e[c];
+            hit |= h[c];
+        }
+        if (__any(hit)) {
+            if (!FA) return true;
+            any = true;
+            bool f = false;
+#pragma unroll
+            for (int c = 0; c < C; c++) {
+                const uint32_t pf = lds_rank<TILE>(x.fe, x.df, s[c]);
+                f |= h[c] && x.fs[pf] < e[c];
+            }
+            if (__any(f)) {
+                *th = true;
+                return true;
             }
         }
-        if (FS) {
-            if (__any(fhit)) { *th = true; return true; }
-            any_hit |= __any(hit);
-        } else if (__any(hit)) {
-            return true;
-        }
-        if (uniform(__shfl(s[0], 0)) >= x_hi) break;
     }
-    return any_hit;
+    return any;
 }
+
+// One pair's lists as the wave sees them: X resident, Y streamed.
+struct PairLists {
+    const uint32_t *xas, *xae, *xfs, *xfe;
+    const uint32_t *yas, *yae, *yfs, *yfe;
+    uint32_t nxa, nxf, nya, nyf;
+};
+
+// Alg. 2's verdict for one pair, by the whole wave.  X is loaded piece by
+// piece (one piece when both its lists are shorter than TILE; that piece
+// stays resident for the next pair with the same `key`).
+template <int TILE, int C>
+__device__ uint8_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, const PairLists &L,
+                             uint32_t search_min, uint32_t lane) {
+    if (L.nxa == 0 || L.nya == 0) return APRIL_TN;
+    const bool one = L.nxa < TILE && L.nxf < TILE;
+    bool aa = false;
+    uint32_t a0 = 0, f0 = 0, k0 = 0;
+    for (;;) {
+        uint32_t a1 = L.nxa, f1 = L.nxf, k1 = kNone;
+        if (!one) {
+            // at most TILE - 1 A elements from a0; the range ends where the
+            // next one starts; then at most TILE - 1 F elements
+            if (L.nxa - a0 > TILE - 1) {
+                a1 = a0 + TILE - 1;
+                k1 = L.xas[a1];
+                f1 = f0 + wave_first_above(L.xfs + f0, L.nxf - f0, k1 - 1, lane);
+            }
+            if (f1 - f0 > TILE - 1) {
+                f1 = f0 + TILE - 1;
+                k1 = L.xfs[f1];
+                a1 = a0 + wave_first_above(L.xas + a0, a1 - a0, k1 - 1, lane);
+            }
+        }
+        if (!one || key != cached) {
+            wave_lds_sync();
+            load_list(res.as, res.ae, L.xas + a0, L.xae + a0, a1 - a0, lane);
+            load_list(res.fs, res.fe, L.xfs + f0, L.xfe + f0, f1 - f0, lane);
+            wave_lds_sync();
+            res.na = a1 - a0;
+            res.nf = f1 - f0;
+            res.da = depth_of(res.na);
+            res.df = depth_of(res.nf);
+            cached = one ? key : kNone;
+        }
+        // Y elements that can meet this piece: end above x_lo, start below x_hi
+        const uint32_t x_lo = max(k0, uniform(res.as[0]));
+        const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
+        const bool narrow = k0 > 0;
+        bool th = false;
+        const uint32_t ja = (narrow || L.nya > search_min) ? wave_first_above(L.yae, L.nya, x_lo, lane) : 0;
+        if (stream_piece<TILE, C, true>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th)) {
+            if (th) return APRIL_TH;
+            aa = true;
+            const uint32_t jf = (narrow || L.nyf > search_min) ? wave_first_above(L.yfe, L.nyf, x_lo, lane) : 0;
+            if (stream_piece<TILE, C, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th))
+                return APRIL_TH;
+        }
+        if (k1 == kNone) break;
+        // next piece: the first elements that end above k1
+        k0 = k1;
+        a0 = L.xae[a1 - 1] > k1 ? a1 - 1 : a1;
+        f0 = (f1 > 0 && L.xfe[f1 - 1] > k1) ? f1 - 1 : f1;
+    }
+    return aa ? APRIL_INDECISIVE : APRIL_TN;
+}
+
+// ------------------------------------------------------------- persistent
 
 // Per-pair metadata a lane holds for its pair of the current grab.
 struct PairMeta {
@@ -297,107 +263,59 @@ __device__ __forceinline__ uint32_t lane_val(uint32_t v, uint32_t k) {
     return __builtin_amdgcn_readlane(v, k);
 }
 
+__device__ __forceinline__ PairLists pair_lists(const FilterArgs &a, bool xs, uint64_t ar0, uint32_t nar,
+                                                uint64_t fr0, uint32_t nfr, uint64_t as0, uint32_t nas,
+                                                uint64_t fs0, uint32_t nfs) {
+    PairLists L;
+    const uint32_t *ras = a.Ar.s + ar0, *rae = a.Ar.e + ar0, *rfs = a.Fr.s + fr0, *rfe = a.Fr.e + fr0;
+    const uint32_t *sas = a.As.s + as0, *sae = a.As.e + as0, *sfs = a.Fs.s + fs0, *sfe = a.Fs.e + fs0;
+    L.xas = xs ? sas : ras; L.xae = xs ? sae : rae; L.xfs = xs ? sfs : rfs; L.xfe = xs ? sfe : rfe;
+    L.yas = xs ? ras : sas; L.yae = xs ? rae : sae; L.yfs = xs ? rfs : sfs; L.yfe = xs ? rfe : sfe;
+    L.nxa = xs ? nas : nar; L.nxf = xs ? nfs : nfr;
+    L.nya = xs ? nar : nas; L.nyf = xs ? nfr : nfs;
+    return L;
+}
+
 template <int TILE, int C>
 __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
-    // wave mode: wave w owns 4*TILE words: A.start, A.end, F.start, F.end
-    // block mode: the whole array is one uint2 tile of 8*TILE entries
     __shared__ uint32_t lds_words[kWavesPerBlock * 4 * TILE];
-    __shared__ unsigned int sh_item;
-    __shared__ int sh_found;
-    __shared__ uint32_t sh_j0;
-    uint2 *lds = reinterpret_cast<uint2 *>(lds_words);
     const FilterArgs &a = b.f;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = uniform(threadIdx.x >> 6);
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
-
-    // ---- BLOCK queue: the workgroup takes one pair at a time (the three
-    // joins of Alg. 2 one after the other, resident side tiled through LDS)
-    const unsigned int n_block = b.tail[Q_BLOCK];
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) sh_item = atomicAdd(&b.head[Q_BLOCK], 1u);
-        __syncthreads();
-        const unsigned int item = sh_item;
-        if (item >= n_block) break;
-        const uint32_t entry = b.queue[Q_BLOCK][item];
-        const uint32_t p = entry & ~kSideS;
-        const bool xs_is_s = entry & kSideS;
-        const uint32_t r = a.r[p], s = a.s[p];
-        const Side sr = side_of(a.Ar, a.Fr, r), ss = side_of(a.As, a.Fs, s);
-        const Side X = xs_is_s ? ss : sr, Y = xs_is_s ? sr : ss;
-        const ListView &XA = xs_is_s ? a.As : a.Ar, &XF = xs_is_s ? a.Fs : a.Fr;
-        const ListView &YA = xs_is_s ? a.Ar : a.As, &YF = xs_is_s ? a.Fr : a.Fs;
-        uint8_t v = APRIL_INDECISIVE;
-        for (int jn = 0; jn < 3; jn++) {
-            // jn 0: X.A x Y.A   jn 1: X.A x Y.F   jn 2: X.F x Y.A
-            const ListView &XL = jn == 2 ? XF : XA;
-            const ListView &YL = jn == 1 ? YF : YA;
-            const uint64_t x0 = jn == 2 ? X.f0 : X.a0, nx = jn == 2 ? X.nf : X.na;
-            const uint64_t y0 = jn == 1 ? Y.f0 : Y.a0, ny = jn == 1 ? Y.nf : Y.na;
-            bool found = false;
-            constexpr uint32_t TB = kWavesPerBlock * 2 * TILE;
-            for (uint64_t t0 = 0; t0 < nx && ny > 0 && !found; t0 += TB) {
-                const uint32_t nt = uint32_t(nx - t0 < TB ? nx - t0 : TB);
-                __syncthreads();
-                load_resident(lds, XL.s + x0 + t0, XL.e + x0 + t0, nt, threadIdx.x, kBlock);
-                if (threadIdx.x == 0) sh_found = 0;
-                __syncthreads();
-                const uint32_t x_lo = lds[0].x, x_hi = lds[nt - 1].y;
-                if (w == 0) {
-                    const uint32_t j0 = uint32_t(ny) > b.search_min
-                                            ? wave_first_end_after(YL.e + y0, uint32_t(ny), x_lo, lane)
-                                            : 0;
-                    if (lane == 0) sh_j0 = j0;
-                }
-                __syncthreads();
-                if (stream_overlap<C>(lds, nt, x_hi, YL.s + y0, YL.e + y0, uint32_t(ny), sh_j0, w,
-                                      kWavesPerBlock, lane, &sh_found)) {
-                    if (lane == 0) sh_found = 1;
-                }
-                __syncthreads();
-                found = sh_found;
-            }
-            if (jn == 0 && !found) { v = APRIL_TN; break; }
-            if (jn > 0 && found) { v = APRIL_TH; break; }
-        }
-        if (threadIdx.x == 0) {
-            a.verdict[p] = v;
-            c_tn += v == APRIL_TN;
-            c_th += v == APRIL_TH;
-            c_ind += v == APRIL_INDECISIVE;
-        }
-    }
-
-    // ---- pairs in input order: each XCD drains its own contiguous range
-    // (pairs close in the input share lists in that XCD's L2), then helps the
-    // others.  A wave takes 64 pairs at a time, one lane per pair's metadata.
     Resident res;
     res.as = lds_words + w * 4 * TILE;
     res.ae = res.as + TILE;
     res.fs = res.ae + TILE;
     res.fe = res.fs + TILE;
-    res.na = res.nf = 0;
-    uint32_t cached = 0xffffffffu;   // resident object id | side bit
+    res.na = res.nf = res.da = res.df = 0;
+    uint32_t cached = kNone;   // resident object id | side bit
+
+    // ---- pairs in input order: each XCD drains its own contiguous range,
+    // then helps the others
     const uint32_t xcds = b.xcds;
     const uint32_t my_xcd = blockIdx.x % xcds;
+    uint32_t grab = b.grab;
     for (uint32_t k = 0; k < xcds; k++) {
         const uint32_t seg = (my_xcd + k) % xcds;
         const uint64_t lo = a.n_pairs * seg / xcds, hi = a.n_pairs * (seg + 1) / xcds;
         for (;;) {
             unsigned int got = 0;
-            if (lane == 0) got = atomicAdd(&b.xhead[seg], 64u);
+            if (lane == 0) got = atomicAdd(&b.xhead[seg], grab);
             const uint64_t g0 = lo + uniform(__shfl(got, 0));
             if (g0 >= hi) break;
+            const uint64_t g1 = min(hi, g0 + grab);
+            if (hi - g1 < b.tail_pairs) grab = b.tail_grab;
             const uint64_t p = g0 + lane;
-            int bin = -1;
-            bool side_s = false;
+            bool seq = false, wave = false, side_s = false;
             PairMeta m{};
-            if (p < hi) {
+            if (p < g1) {
                 m.p = uint32_t(p);
                 m.r = a.r[p];
                 m.s = a.s[p];
-                if (m.r < a.n_r && m.s < a.n_s) {
+                if (m.r >= a.n_r || m.s >= a.n_s) {
+                    a.verdict[p] = APRIL_BAD_PAIR;
+                } else {
                     const uint64_t ar0 = a.Ar.off[m.r], ar1 = a.Ar.off[m.r + 1];
                     const uint64_t fr0 = a.Fr.off[m.r], fr1 = a.Fr.off[m.r + 1];
                     const uint64_t as0 = a.As.off[m.s], as1 = a.As.off[m.s + 1];
@@ -407,63 +325,35 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
                     m.as0lo = uint32_t(as0); m.as0hi = uint32_t(as0 >> 32); m.nas = uint32_t(as1 - as0);
                     m.fs0lo = uint32_t(fs0); m.fs0hi = uint32_t(fs0 >> 32); m.nfs = uint32_t(fs1 - fs0);
                     const uint32_t mr = max(m.nar, m.nfr), ms = max(m.nas, m.nfs);
-                    if (max(mr, ms) <= b.thread_max) bin = Q_THREAD;
-                    else if (mr <= TILE) bin = Q_WAVE;
-                    else if (ms <= TILE) { bin = Q_WAVE; side_s = true; }
-                    // else: workgroup queue, done above
+                    if (max(mr, ms) <= b.thread_max) seq = true;
+                    else if (mr < TILE) wave = true;
+                    else if (ms < TILE || ms < mr) { wave = true; side_s = true; }
+                    else wave = true;
                 }
             }
-            // wave bin: one pair after another, the wave cooperating
-            uint64_t todo = __ballot(bin == Q_WAVE);
+            // one pair after another, the wave cooperating
+            uint64_t todo = __ballot(wave);
             const uint64_t sides = __ballot(side_s);
             while (todo) {
                 const uint32_t k2 = uint32_t(__builtin_ctzll(todo));
                 todo &= todo - 1;
                 const bool xs = (sides >> k2) & 1;
-                const uint32_t pp = lane_val(m.p, k2);
-                const uint32_t xo = lane_val(xs ? m.s : m.r, k2);
-                const uint64_t xa0 = join64(lane_val(xs ? m.as0lo : m.ar0lo, k2), lane_val(xs ? m.as0hi : m.ar0hi, k2));
-                const uint32_t nxa = lane_val(xs ? m.nas : m.nar, k2);
-                const uint64_t xf0 = join64(lane_val(xs ? m.fs0lo : m.fr0lo, k2), lane_val(xs ? m.fs0hi : m.fr0hi, k2));
-                const uint32_t nxf = lane_val(xs ? m.nfs : m.nfr, k2);
-                const uint64_t ya0 = join64(lane_val(xs ? m.ar0lo : m.as0lo, k2), lane_val(xs ? m.ar0hi : m.as0hi, k2));
-                const uint32_t nya = lane_val(xs ? m.nar : m.nas, k2);
-                const uint64_t yf0 = join64(lane_val(xs ? m.fr0lo : m.fs0lo, k2), lane_val(xs ? m.fr0hi : m.fs0hi, k2));
-                const uint32_t nyf = lane_val(xs ? m.nfr : m.nfs, k2);
-                const ListView &XA = xs ? a.As : a.Ar, &XF = xs ? a.Fs : a.Fr;
-                const ListView &YA = xs ? a.Ar : a.As, &YF = xs ? a.Fr : a.Fs;
-                const uint32_t key = xo | (xs ? kSideS : 0u);
-                if (key != cached) {
-                    wave_lds_sync();
-                    for (uint32_t t = lane; t < nxa; t += 64) { res.as[t] = XA.s[xa0 + t]; res.ae[t] = XA.e[xa0 + t]; }
-                    for (uint32_t t = lane; t < nxf; t += 64) { res.fs[t] = XF.s[xf0 + t]; res.fe[t] = XF.e[xf0 + t]; }
-                    wave_lds_sync();
-                    res.na = nxa;
-                    res.nf = nxf;
-                    cached = key;
-                }
-                // AA, with FA on every AA-overlapping element (F inside A)
-                bool th = false;
-                const bool aa = stream_join_resident<C>(res.as, res.ae, res.na, res.fs, res.fe, res.nf,
-                                                        YA.s + ya0, YA.e + ya0, nya, b.search_min, lane,
-                                                        &th);
-                uint8_t v;
-                if (!aa) v = APRIL_TN;
-                else if (th) v = APRIL_TH;
-                else if (stream_join_resident<C>(res.as, res.ae, res.na, nullptr, nullptr, 0,
-                                                 YF.s + yf0, YF.e + yf0, nyf, b.search_min, lane,
-                                                 &th))
-                    v = APRIL_TH;
-                else v = APRIL_INDECISIVE;
+                const PairLists L = pair_lists(
+                    a, xs, join64(lane_val(m.ar0lo, k2), lane_val(m.ar0hi, k2)), lane_val(m.nar, k2),
+                    join64(lane_val(m.fr0lo, k2), lane_val(m.fr0hi, k2)), lane_val(m.nfr, k2),
+                    join64(lane_val(m.as0lo, k2), lane_val(m.as0hi, k2)), lane_val(m.nas, k2),
+                    join64(lane_val(m.fs0lo, k2), lane_val(m.fs0hi, k2)), lane_val(m.nfs, k2));
+                const uint32_t key = lane_val(xs ? m.s : m.r, k2) | (xs ? kSideS : 0u);
+                const uint8_t v = wave_pair<TILE, C>(res, cached, key, L, b.search_min, lane);
                 if (lane == 0) {
-                    a.verdict[pp] = v;
+                    a.verdict[lane_val(m.p, k2)] = v;
                     c_tn += v == APRIL_TN;
                     c_th += v == APRIL_TH;
                     c_ind += v == APRIL_INDECISIVE;
                 }
             }
-            // thread bin: every such lane runs Alg. 2 on its own pair
-            if (bin == Q_THREAD) {
+            // very short lists: every such lane runs Alg. 2 on its own pair
+            if (seq) {
                 const uint64_t ar0 = join64(m.ar0lo, m.ar0hi), fr0 = join64(m.fr0lo, m.fr0hi);
                 const uint64_t as0 = join64(m.as0lo, m.as0hi), fs0 = join64(m.fs0lo, m.fs0hi);
                 uint32_t x, y;
@@ -509,7 +399,10 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     }
     uint64_t blocks = uint64_t(cus) * per_cu;
     if (waves) blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_batched<TILE, C><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(b);
+    // a range is near its end once its waves have about two full grabs each left
+    BatchArgs bb = b;
+    bb.tail_pairs = 2ull * b.grab * kWavesPerBlock * ((blocks + b.xcds - 1) / b.xcds);
+    k_batched<TILE, C><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
     APRIL_HIP_TRY(hipGetLastError());
     return APRIL_OK;
 }
@@ -526,7 +419,7 @@ int launch_t(const BatchArgs &b, uint32_t chunk, int cus, uint32_t waves, hipStr
 
 }  // namespace
 
-uint64_t batched_workspace_bytes(uint64_t n_pairs) { return kCtrBytes + 4 * (n_pairs ? n_pairs : 1); }
+uint64_t batched_workspace_bytes(uint64_t) { return kCtrBytes; }
 
 int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? cus / 32 : 1; }
 
@@ -536,21 +429,14 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     const uint32_t chunk = o.chunk ? o.chunk : 1;
     BatchArgs b;
     b.f = a;
-    char *ws = static_cast<char *>(workspace);
-    b.tail = reinterpret_cast<unsigned int *>(ws);
-    b.head = b.tail + 3;
-    b.xhead = b.tail + 6;
+    b.xhead = static_cast<unsigned int *>(workspace);
     b.xcds = uint32_t(xcd_count(cus));
-    b.queue[Q_THREAD] = b.queue[Q_WAVE] = nullptr;
-    b.queue[Q_BLOCK] = reinterpret_cast<uint32_t *>(ws + kCtrBytes);
     b.thread_max = o.thread_max ? o.thread_max : 8;
     b.search_min = o.search_min ? o.search_min : 512;
     b.grab = 64;
+    b.tail_grab = 8;
     if (b.thread_max >= tile) return fail(APRIL_E_INVALID, "thread_max must be below tile");
-    k_zero_batch<<<1, 64, 0, stream>>>(b.tail, a.counts);
-    APRIL_HIP_TRY(hipGetLastError());
-    const uint64_t bin_blocks = std::min<uint64_t>((a.n_pairs + 255) / 256, uint64_t(cus) * 8);
-    k_bin<<<dim3(uint32_t(std::max<uint64_t>(bin_blocks, 1))), dim3(256), 0, stream>>>(b, tile);
+    k_zero_batch<<<1, 64, 0, stream>>>(b.xhead, a.counts);
     APRIL_HIP_TRY(hipGetLastError());
     switch (tile) {
         case 128: return launch_t<128>(b, chunk, cus, o.waves, stream);

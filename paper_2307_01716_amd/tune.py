@@ -2,8 +2,9 @@
 
 Sweeps the batched schedule's knobs on a workload that is already resident
 on the device -- LDS tile per wavefront, streamed chunk per lane, the length above which
-streamed lists are range-searched first, and the lane-per-pair threshold -- timing each
-setting with HIP events, and returns the fastest.  Results can be written to
+streamed lists are range-searched first, the lane-per-pair threshold and the
+resident wavefronts per SIMD -- timing each setting with HIP events, and
+returns the fastest.  Results can be written to
 a JSON table keyed by device and a workload signature, and read back by
 callers that want to skip the sweep.
 """
@@ -20,10 +21,21 @@ from . import april
 
 GRID = {
     "tile": (128, 256, 512),
-    "chunk": (1, 2, 4),
+    "chunk": (1, 2),
     "search_min": (512, 4096),
     "thread_max": (8,),
+    "waves_per_simd": (0, 4, 6),
 }
+
+
+def _call_cfg(cfg: dict) -> dict:
+    """Knobs as april_filter_pairs takes them: waves per SIMD (0 = as many as
+    fit) becomes a count of resident wavefronts."""
+    out = {k: v for k, v in cfg.items() if k != "waves_per_simd"}
+    wps = cfg.get("waves_per_simd", 0)
+    if wps:
+        out["waves"] = wps * 4 * april.april_device_info()["compute_units"]
+    return out
 
 
 def signature(n_pairs: int, lists_r, lists_s) -> str:
@@ -36,9 +48,11 @@ def time_config(dR, dS, r, s, verdict, counts, workspace, reps=3, **cfg) -> floa
 
     stream = torch.cuda.current_stream()
 
+    kw = _call_cfg(cfg)
+
     def run():
         april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_BATCHED,
-                                 workspace=workspace, stream=stream, **cfg)
+                                 workspace=workspace, stream=stream, **kw)
 
     run()
     torch.cuda.synchronize()
@@ -70,6 +84,11 @@ def sweep(dR, dS, r, s, verdict, counts, workspace, grid=None, reps=3, log=None)
     best = min(table, key=lambda t: t["ms"])
     cfg = {k: best[k] for k in keys}
     return cfg, best["ms"], table
+
+
+def call_config(cfg: dict) -> dict:
+    """The keyword arguments of april_filter_pairs for a swept setting."""
+    return _call_cfg(cfg)
 
 
 def save(path: str, device: str, sig: str, cfg: dict, ms: float, table) -> None:

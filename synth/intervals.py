@@ -82,3 +82,21 @@ def sub_lists(rng: np.random.Generator, start: np.ndarray, end: np.ndarray, p: f
     b = a + 1 + (rng.random(len(s0)) * (e0 - a)).astype(np.int64)
     b = np.minimum(b, e0)
     return a.astype(np.uint32), b.astype(np.uint32)
+
+
+def fragmented_sub_lists(rng: np.random.Generator, start: np.ndarray, end: np.ndarray, max_parts: int):
+    """A list inside (start, end) with up to `max_parts` intervals inside each
+    interval (so it can be much longer than the list it lies in): 2q distinct
+    sorted points in [s, e] give q non-touching sub-intervals of [s, e)."""
+    out_s, out_e = [], []
+    for s, e in zip(np.asarray(start, np.int64), np.asarray(end, np.int64)):
+        q = int(rng.integers(0, max_parts + 1))
+        q = min(q, int(e - s + 1) // 2)
+        if q == 0:
+            continue
+        v = np.sort(rng.choice(int(e - s + 1), size=2 * q, replace=False)) + s
+        out_s.append(v[0::2])
+        out_e.append(v[1::2])
+    if not out_s:
+        return np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+    return np.concatenate(out_s).astype(np.uint32), np.concatenate(out_e).astype(np.uint32)

@@ -21,7 +21,7 @@ import pytest
 
 import oracle
 import synth
-from synth.intervals import ListSet, complement_list, random_lists, sub_lists
+from synth.intervals import ListSet, complement_list, fragmented_sub_lists, random_lists, sub_lists
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +64,8 @@ GRID = (0.0, 0.0, float(1 << 16) * 2.0 ** -30 * (1 << 16), 16)
 
 # schedules under test: plain, batched with defaults, and batched tunings
 # that push pairs through every bin and code path (lane-per-pair bin, wave
-# bin with either side resident, workgroup bin with multi-tile residents,
-# range search on every streamed list)
+# bin with either side resident, big pairs with the resident lists cut into
+# pieces, range search on every streamed list)
 SCHEDULES = {
     "plain": dict(schedule=april.SCHED_PLAIN),
     "batched": dict(schedule=april.SCHED_BATCHED),
@@ -84,12 +84,20 @@ def _random_collection(rng, n, kind):
                                 1000, 4095, 4097]))
         elif kind == "long":
             L = int(rng.choice([1, 3, 10_000, 65_536, 100_000]))
+        elif kind == "fragmented":
+            L = int(rng.choice([1, 2, 5, 40, 300]))
         else:
             L = int(rng.integers(0, 300))
         lo = int(rng.integers(0, 1 << 20))
         span = max(4 * L + 8, int(rng.integers(2 * L + 2, 64 * L + 64)))
-        a = random_lists(rng, max(L, 1), lo, lo + span)
-        f = sub_lists(rng, *a, p=float(rng.random()))    # F inside A, as for polygons
+        if kind == "fragmented":
+            # few A intervals holding many F intervals each: F longer than A
+            span = max(span, 4000 * L)
+            a = random_lists(rng, max(L, 1), lo, lo + span)
+            f = fragmented_sub_lists(rng, *a, max_parts=int(rng.choice([0, 3, 60, 400])))
+        else:
+            a = random_lists(rng, max(L, 1), lo, lo + span)
+            f = sub_lists(rng, *a, p=float(rng.random()))    # F inside A, as for polygons
         A.append(a)
         F.append(f)
     a = ListSet.from_lists(A)
@@ -99,9 +107,9 @@ def _random_collection(rng, n, kind):
 
 @pytest.mark.parametrize("sched", list(SCHEDULES))
 @pytest.mark.parametrize("kind,n,P", [("mixed", 400, 20_000), ("edges", 300, 20_000),
-                                      ("long", 12, 150)])
+                                      ("long", 12, 150), ("fragmented", 60, 3000)])
 def test_random_lists(kind, n, P, sched):
-    rng = np.random.default_rng({"mixed": 1, "edges": 2, "long": 3}[kind])
+    rng = np.random.default_rng({"mixed": 1, "edges": 2, "long": 3, "fragmented": 4}[kind])
     say(f"[random lists] kind={kind} n={n} P={P} schedule={sched}")
     LR = _random_collection(rng, n, kind)
     LS = _random_collection(rng, n, kind)

@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--schedule", choices=["both", "plain", "batched"], default="both")
     ap.add_argument("--no-tune", action="store_true", help="batched: library defaults, no sweep")
+    ap.add_argument("--config", default="",
+                    help="batched: fixed tuning instead of a sweep, e.g. tile=256,waves_per_simd=6")
     ap.add_argument("--no-graph", action="store_true", help="batched: eager launches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times (reference dispatches for HBM counters)")
@@ -186,7 +188,10 @@ def main():
         from paper_2307_01716_amd import tune
         ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
         cfg, kw = {}, {}
-        if not args.no_tune:
+        if args.config:
+            cfg = {k: int(v) for k, v in (kv.split("=") for kv in args.config.split(","))}
+            kw = tune.call_config(cfg)
+        elif not args.no_tune:
             t0 = time.time()
             cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3, log=log)
             log(f"autotune: {len(table)} settings in {time.time() - t0:.1f}s; best {cfg} "

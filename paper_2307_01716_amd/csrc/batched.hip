@@ -26,7 +26,7 @@
 //
 // LDS layout and search.  A wave's resident lists are four arrays of TILE
 // words (A.start, A.end, F.start, F.end).  Slots from the list's length up
-// to the next power of two hold 0xFFFFFFFF, which is never at or below a
+// to TILE hold 0xFFFFFFFF, which is never at or below a
 // start value (starts are below 2^32 - 1), so the search for i*(j) is a
 // fixed sequence of compare-and-step rounds with no bounds tests, and the
 // slot it lands on past the list's end holds a start that overlaps nothing.
@@ -104,35 +104,65 @@ __device__ uint32_t wave_first_above(const uint32_t *__restrict__ v, uint32_t m,
     return mask ? lo + uint32_t(__builtin_ctzll(mask)) : hi;
 }
 
-// Resident lists of one wave (SoA in LDS, sentinel-padded) and their search
-// depths: 2^depth is the smallest power of two above the length.
+// Resident lists of one wave: SoA in LDS, padded with sentinels to TILE
+// entries.
 struct Resident {
     uint32_t *as, *ae, *fs, *fe;
-    uint32_t na, nf, da, df;
+    uint32_t na, nf;
 };
 
-__device__ __forceinline__ uint32_t depth_of(uint32_t n) { return 32u - __clz(n); }
-
-// number of entries <= key in E (first i with E[i] > key); E holds a sorted
-// list padded with 0xFFFFFFFF to 2^depth entries, depth <= log2(TILE)
+// number of entries <= key in E (first i with E[i] > key): E holds a sorted
+// list padded with 0xFFFFFFFF to TILE entries, so log2(TILE) fixed rounds
+// need no bounds tests and no per-round branch
 template <int TILE>
-__device__ __forceinline__ uint32_t lds_rank(const uint32_t *E, uint32_t depth, uint32_t key) {
+__device__ __forceinline__ uint32_t lds_rank(const uint32_t *E, uint32_t key) {
     const uint32_t *p = E;   // stepping the address keeps each round to one add
 #pragma unroll
-    for (uint32_t S = TILE / 2; S > 0; S >>= 1) {
-        if (S < (1u << depth)) p = p[S - 1] <= key ? p + S : p;
-    }
+    for (uint32_t S = TILE / 2; S > 0; S >>= 1) p = p[S - 1] <= key ? p + S : p;
     return uint32_t(p - E);
 }
 
-// copy n < TILE intervals into a resident pair of arrays and pad them
-__device__ __forceinline__ void load_list(uint32_t *S, uint32_t *E, const uint32_t *__restrict__ gs,
-                                          const uint32_t *__restrict__ ge, uint32_t n, uint32_t lane) {
-    const uint32_t P = 1u << depth_of(n);
-    for (uint32_t t = lane; t < P; t += 64) {
-        const bool v = t < n;
-        S[t] = v ? gs[t] : 0xffffffffu;
-        E[t] = v ? ge[t] : 0xffffffffu;
+// the same search in two arrays at once (independent LDS reads overlap)
+template <int TILE>
+__device__ __forceinline__ void lds_rank2(const uint32_t *E1, const uint32_t *E2, uint32_t key, uint32_t &r1,
+                                          uint32_t &r2) {
+    const uint32_t *p = E1, *q = E2;
+#pragma unroll
+    for (uint32_t S = TILE / 2; S > 0; S >>= 1) {
+        const uint32_t u = p[S - 1], v = q[S - 1];
+        p = u <= key ? p + S : p;
+        q = v <= key ? q + S : q;
+    }
+    r1 = uint32_t(p - E1);
+    r2 = uint32_t(q - E2);
+}
+
+// Copy X's A and F lists (na, nf < TILE intervals) into the resident arrays,
+// padding all TILE slots: every global load is issued before the first LDS
+// write, so the copy costs one memory round trip.
+template <int TILE>
+__device__ __forceinline__ void load_resident(const Resident &x, const uint32_t *__restrict__ as,
+                                              const uint32_t *__restrict__ ae, uint32_t na,
+                                              const uint32_t *__restrict__ fs, const uint32_t *__restrict__ fe,
+                                              uint32_t nf, uint32_t lane) {
+    constexpr int R = TILE / 64;
+    uint32_t vas[R], vae[R], vfs[R], vfe[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+        const uint32_t t = i * 64 + lane;
+        const bool a = t < na, f = t < nf;
+        vas[i] = a ? as[t] : 0xffffffffu;
+        vae[i] = a ? ae[t] : 0xffffffffu;
+        vfs[i] = f ? fs[t] : 0xffffffffu;
+        vfe[i] = f ? fe[t] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+        const uint32_t t = i * 64 + lane;
+        x.as[t] = vas[i];
+        x.ae[t] = vae[i];
+        x.fs[t] = vfs[i];
+        x.fe[t] = vfe[i];
     }
 }
 
@@ -156,23 +186,25 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
         }
         // this chunk and all later ones start at or after the piece's end
         if (uniform(s[0]) >= stop) break;
-        bool h[C];
-        bool hit = false;
+        bool hit = false, f = false;
 #pragma unroll
         for (int c = 0; c < C; c++) {
-            const uint32_t pos = lds_rank<TILE>(x.ae, x.da, s[c]);
-            h[c] = x.as[pos] < e[c];
-            hit |= h[c];
+            if (FA) {
+                // the F search runs beside the A search; its answer counts
+                // only where the element overlaps the A-list
+                uint32_t pa, pf;
+                lds_rank2<TILE>(x.ae, x.fe, s[c], pa, pf);
+                const uint32_t sa = x.as[pa], sf = x.fs[pf];
+                const bool h = sa < e[c];
+                hit |= h;
+                f |= h & (sf < e[c]);
+            } else {
+                hit |= x.as[lds_rank<TILE>(x.ae, s[c])] < e[c];
+            }
         }
         if (__any(hit)) {
             if (!FA) return true;
             any = true;
-            bool f = false;
-#pragma unroll
-            for (int c = 0; c < C; c++) {
-                const uint32_t pf = lds_rank<TILE>(x.fe, x.df, s[c]);
-                f |= h[c] && x.fs[pf] < e[c];
-            }
             if (__any(f)) {
                 *th = true;
                 return true;
@@ -217,13 +249,10 @@ __device__ uint8_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, cons
         }
         if (!one || key != cached) {
             wave_lds_sync();
-            load_list(res.as, res.ae, L.xas + a0, L.xae + a0, a1 - a0, lane);
-            load_list(res.fs, res.fe, L.xfs + f0, L.xfe + f0, f1 - f0, lane);
+            load_resident<TILE>(res, L.xas + a0, L.xae + a0, a1 - a0, L.xfs + f0, L.xfe + f0, f1 - f0, lane);
             wave_lds_sync();
             res.na = a1 - a0;
             res.nf = f1 - f0;
-            res.da = depth_of(res.na);
-            res.df = depth_of(res.nf);
             cached = one ? key : kNone;
         }
         // Y elements that can meet this piece: end above x_lo, start below x_hi
@@ -250,19 +279,18 @@ __device__ uint8_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, cons
 
 // ------------------------------------------------------------- persistent
 
-// Per-pair metadata a lane holds for its pair of the current grab.
-struct PairMeta {
-    uint32_t p, r, s;
-    uint32_t ar0lo, ar0hi, nar, fr0lo, fr0hi, nfr;   // offsets split in 32-bit halves
-    uint32_t as0lo, as0hi, nas, fs0lo, fs0hi, nfs;
-};
-
 __device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) { return (uint64_t(hi) << 32) | lo; }
 
 __device__ __forceinline__ uint32_t lane_val(uint32_t v, uint32_t k) {
     return __builtin_amdgcn_readlane(v, k);
 }
 
+__device__ __forceinline__ const uint32_t *lane_ptr(const uint32_t *p, uint32_t k) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    return reinterpret_cast<const uint32_t *>(join64(lane_val(uint32_t(v), k), lane_val(uint32_t(v >> 32), k)));
+}
+
+// One pair's lists with X = S's object when `xs`, else R's.
 __device__ __forceinline__ PairLists pair_lists(const FilterArgs &a, bool xs, uint64_t ar0, uint32_t nar,
                                                 uint64_t fr0, uint32_t nfr, uint64_t as0, uint32_t nas,
                                                 uint64_t fs0, uint32_t nfs) {
@@ -276,10 +304,19 @@ __device__ __forceinline__ PairLists pair_lists(const FilterArgs &a, bool xs, ui
     return L;
 }
 
+// The pair lane k holds, as the whole wave sees it (scalar registers).
+__device__ __forceinline__ PairLists lane_pair(const PairLists &m, uint32_t k) {
+    PairLists L;
+    L.xas = lane_ptr(m.xas, k); L.xae = lane_ptr(m.xae, k); L.xfs = lane_ptr(m.xfs, k); L.xfe = lane_ptr(m.xfe, k);
+    L.yas = lane_ptr(m.yas, k); L.yae = lane_ptr(m.yae, k); L.yfs = lane_ptr(m.yfs, k); L.yfe = lane_ptr(m.yfe, k);
+    L.nxa = lane_val(m.nxa, k); L.nxf = lane_val(m.nxf, k);
+    L.nya = lane_val(m.nya, k); L.nyf = lane_val(m.nyf, k);
+    return L;
+}
+
 template <int TILE, int C>
 __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
     __shared__ uint32_t lds_words[kWavesPerBlock * 4 * TILE];
-    const FilterArgs &a = b.f;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = uniform(threadIdx.x >> 6);
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
@@ -288,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
     res.ae = res.as + TILE;
     res.fs = res.ae + TILE;
     res.fe = res.fs + TILE;
-    res.na = res.nf = res.da = res.df = 0;
+    res.na = res.nf = 0;
     uint32_t cached = kNone;   // resident object id | side bit
 
     // ---- pairs in input order: each XCD drains its own contiguous range,
@@ -298,81 +335,80 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
     uint32_t grab = b.grab;
     for (uint32_t k = 0; k < xcds; k++) {
         const uint32_t seg = (my_xcd + k) % xcds;
-        const uint64_t lo = a.n_pairs * seg / xcds, hi = a.n_pairs * (seg + 1) / xcds;
+        const uint64_t lo = b.f.n_pairs * seg / xcds, hi = b.f.n_pairs * (seg + 1) / xcds;
         for (;;) {
+            // The arguments are read afresh for every grab (through a pointer
+            // the compiler cannot see through), so they hold no scalar
+            // registers while the grab's pairs are processed.
+            const BatchArgs *pb = &b;
+            asm volatile("" : "+s"(pb));
+            const FilterArgs &a = pb->f;
             unsigned int got = 0;
-            if (lane == 0) got = atomicAdd(&b.xhead[seg], grab);
+            if (lane == 0) got = atomicAdd(&pb->xhead[seg], grab);
             const uint64_t g0 = lo + uniform(__shfl(got, 0));
             if (g0 >= hi) break;
             const uint64_t g1 = min(hi, g0 + grab);
-            if (hi - g1 < b.tail_pairs) grab = b.tail_grab;
+            if (hi - g1 < pb->tail_pairs) grab = pb->tail_grab;
             const uint64_t p = g0 + lane;
-            bool seq = false, wave = false, side_s = false;
-            PairMeta m{};
+            bool seq = false, wave = false;
+            // lane k's verdict for pair g0 + k, stored once per grab (a
+            // store per pair would make each pair wait for the last one's)
+            uint32_t vv = APRIL_BAD_PAIR;
+            // lane k's pair: its lists with X the object to keep resident
+            PairLists m{};
+            uint32_t key = kNone;
             if (p < g1) {
-                m.p = uint32_t(p);
-                m.r = a.r[p];
-                m.s = a.s[p];
-                if (m.r >= a.n_r || m.s >= a.n_s) {
-                    a.verdict[p] = APRIL_BAD_PAIR;
-                } else {
-                    const uint64_t ar0 = a.Ar.off[m.r], ar1 = a.Ar.off[m.r + 1];
-                    const uint64_t fr0 = a.Fr.off[m.r], fr1 = a.Fr.off[m.r + 1];
-                    const uint64_t as0 = a.As.off[m.s], as1 = a.As.off[m.s + 1];
-                    const uint64_t fs0 = a.Fs.off[m.s], fs1 = a.Fs.off[m.s + 1];
-                    m.ar0lo = uint32_t(ar0); m.ar0hi = uint32_t(ar0 >> 32); m.nar = uint32_t(ar1 - ar0);
-                    m.fr0lo = uint32_t(fr0); m.fr0hi = uint32_t(fr0 >> 32); m.nfr = uint32_t(fr1 - fr0);
-                    m.as0lo = uint32_t(as0); m.as0hi = uint32_t(as0 >> 32); m.nas = uint32_t(as1 - as0);
-                    m.fs0lo = uint32_t(fs0); m.fs0hi = uint32_t(fs0 >> 32); m.nfs = uint32_t(fs1 - fs0);
-                    const uint32_t mr = max(m.nar, m.nfr), ms = max(m.nas, m.nfs);
-                    if (max(mr, ms) <= b.thread_max) seq = true;
-                    else if (mr < TILE) wave = true;
-                    else if (ms < TILE || ms < mr) { wave = true; side_s = true; }
+                const uint32_t r = a.r[p], s = a.s[p];
+                if (r < a.n_r && s < a.n_s) {
+                    const uint64_t ar0 = a.Ar.off[r], fr0 = a.Fr.off[r];
+                    const uint64_t as0 = a.As.off[s], fs0 = a.Fs.off[s];
+                    const uint32_t nar = uint32_t(a.Ar.off[r + 1] - ar0), nfr = uint32_t(a.Fr.off[r + 1] - fr0);
+                    const uint32_t nas = uint32_t(a.As.off[s + 1] - as0), nfs = uint32_t(a.Fs.off[s + 1] - fs0);
+                    const uint32_t mr = max(nar, nfr), ms = max(nas, nfs);
+                    // R resident when its lists fit a tile; else S when its
+                    // do or when neither does and S's are shorter
+                    const bool xs = !(mr < TILE) && (ms < TILE || ms < mr);
+                    if (max(mr, ms) <= pb->thread_max) seq = true;
                     else wave = true;
+                    m = pair_lists(a, xs, ar0, nar, fr0, nfr, as0, nas, fs0, nfs);
+                    key = (xs ? s : r) | (xs ? kSideS : 0u);
                 }
             }
             // one pair after another, the wave cooperating
             uint64_t todo = __ballot(wave);
-            const uint64_t sides = __ballot(side_s);
+            const uint32_t search_min = pb->search_min;
             while (todo) {
                 const uint32_t k2 = uint32_t(__builtin_ctzll(todo));
                 todo &= todo - 1;
-                const bool xs = (sides >> k2) & 1;
-                const PairLists L = pair_lists(
-                    a, xs, join64(lane_val(m.ar0lo, k2), lane_val(m.ar0hi, k2)), lane_val(m.nar, k2),
-                    join64(lane_val(m.fr0lo, k2), lane_val(m.fr0hi, k2)), lane_val(m.nfr, k2),
-                    join64(lane_val(m.as0lo, k2), lane_val(m.as0hi, k2)), lane_val(m.nas, k2),
-                    join64(lane_val(m.fs0lo, k2), lane_val(m.fs0hi, k2)), lane_val(m.nfs, k2));
-                const uint32_t key = lane_val(xs ? m.s : m.r, k2) | (xs ? kSideS : 0u);
-                const uint8_t v = wave_pair<TILE, C>(res, cached, key, L, b.search_min, lane);
-                if (lane == 0) {
-                    a.verdict[lane_val(m.p, k2)] = v;
-                    c_tn += v == APRIL_TN;
-                    c_th += v == APRIL_TH;
-                    c_ind += v == APRIL_INDECISIVE;
-                }
+                const PairLists L = lane_pair(m, k2);
+                const uint32_t v = wave_pair<TILE, C>(res, cached, lane_val(key, k2), L, search_min, lane);
+                vv = lane == k2 ? v : vv;
             }
             // very short lists: every such lane runs Alg. 2 on its own pair
+            // (X and Y stand for R and S in either order; the verdict is
+            // symmetric)
             if (seq) {
-                const uint64_t ar0 = join64(m.ar0lo, m.ar0hi), fr0 = join64(m.fr0lo, m.fr0hi);
-                const uint64_t as0 = join64(m.as0lo, m.as0hi), fs0 = join64(m.fs0lo, m.fs0hi);
                 uint32_t x, y;
-                uint8_t v;
-                if (!seq_join(a.Ar.s + ar0, a.Ar.e + ar0, m.nar, a.As.s + as0, a.As.e + as0, m.nas, &x, &y))
+                uint32_t v;
+                if (!seq_join(m.xas, m.xae, m.nxa, m.yas, m.yae, m.nya, &x, &y))
                     v = APRIL_TN;
-                else if (seq_join(a.Ar.s + ar0, a.Ar.e + ar0, m.nar, a.Fs.s + fs0, a.Fs.e + fs0, m.nfs, &x, &y) ||
-                         seq_join(a.Fr.s + fr0, a.Fr.e + fr0, m.nfr, a.As.s + as0, a.As.e + as0, m.nas, &x, &y))
+                else if (seq_join(m.xas, m.xae, m.nxa, m.yfs, m.yfe, m.nyf, &x, &y) ||
+                         seq_join(m.xfs, m.xfe, m.nxf, m.yas, m.yae, m.nya, &x, &y))
                     v = APRIL_TH;
                 else
                     v = APRIL_INDECISIVE;
-                a.verdict[m.p] = v;
-                c_tn += v == APRIL_TN;
-                c_th += v == APRIL_TH;
-                c_ind += v == APRIL_INDECISIVE;
+                vv = v;
+            }
+            if (p < g1) {
+                pb->f.verdict[p] = uint8_t(vv);
+                c_tn += vv == APRIL_TN;
+                c_th += vv == APRIL_TH;
+                c_ind += vv == APRIL_INDECISIVE;
             }
         }
     }
 
+    const FilterArgs &a = b.f;
     if (a.counts) {
         for (int off = 32; off > 0; off >>= 1) {
             c_tn += __shfl_down(c_tn, off);

@@ -25,7 +25,7 @@
 // indecisive.
 //
 // LDS layout and search.  A wave's resident lists are four arrays of TILE
-// words (A.start, A.end, F.start, F.end).  Slots from the list's length up
+// words (A.end, A.start, F.end, F.start).  Slots from the list's length up
 // to TILE hold 0xFFFFFFFF, which is never at or below a
 // start value (starts are below 2^32 - 1), so the search for i*(j) is a
 // fixed sequence of compare-and-step rounds with no bounds tests, and the
@@ -81,6 +81,20 @@ __global__ __launch_bounds__(64) void k_zero_batch(unsigned int *ctr, unsigned l
 
 // ------------------------------------------------------------ join pieces
 
+// v[i] through the global address space (scalar base + 32-bit byte offset)
+__device__ __forceinline__ uint32_t gload(const uint32_t *v, uint32_t i) {
+    const char __attribute__((address_space(1))) *b = (const char __attribute__((address_space(1))) *)v;
+    return *(const uint32_t __attribute__((address_space(1))) *)(b + (i << 2));
+}
+
+__device__ __forceinline__ uint64_t gload64(const uint64_t *v, uint64_t i) {
+    return ((const uint64_t __attribute__((address_space(1))) *)v)[i];
+}
+
+__device__ __forceinline__ uint32_t gload32(const uint32_t *v, uint64_t i) {
+    return ((const uint32_t __attribute__((address_space(1))) *)v)[i];
+}
+
 // first j in [0, m) with v[j] > key (m if none), v sorted: wave-cooperative
 // 64-ary search, one global round trip per factor of 64
 __device__ uint32_t wave_first_above(const uint32_t *__restrict__ v, uint32_t m, uint32_t key, uint32_t lane) {
@@ -88,7 +102,7 @@ __device__ uint32_t wave_first_above(const uint32_t *__restrict__ v, uint32_t m,
     while (hi - lo > 64) {
         const uint64_t step = (uint64_t(hi - lo) + 63) >> 6;
         const uint64_t probe = lo + (lane + 1) * step - 1;
-        const bool pred = probe >= hi ? true : (v[probe] > key);
+        const bool pred = probe >= hi ? true : (gload(v, uint32_t(probe)) > key);
         const uint64_t mask = __ballot(pred);
         if (!mask) { lo = hi; break; }
         const uint64_t f = __builtin_ctzll(mask);
@@ -99,7 +113,7 @@ __device__ uint32_t wave_first_above(const uint32_t *__restrict__ v, uint32_t m,
     }
     if (hi - lo == 0) return lo;
     const uint32_t j = lo + lane;
-    const bool pred = j >= hi ? true : (v[j] > key);
+    const bool pred = j >= hi ? true : (gload(v, j) > key);
     const uint64_t mask = __ballot(pred);
     return mask ? lo + uint32_t(__builtin_ctzll(mask)) : hi;
 }
@@ -111,21 +125,22 @@ struct Resident {
     uint32_t na, nf;
 };
 
-// number of entries <= key in E (first i with E[i] > key): E holds a sorted
-// list padded with 0xFFFFFFFF to TILE entries, so log2(TILE) fixed rounds
-// need no bounds tests and no per-round branch
+// Search of a resident end array E (sorted, padded with 0xFFFFFFFF to TILE
+// entries): the address of the first entry above key, in log2(TILE) fixed
+// rounds with no bounds tests and no per-round branch.  The matching start
+// lies TILE entries further on (the arrays are laid out end, start).
 template <int TILE>
-__device__ __forceinline__ uint32_t lds_rank(const uint32_t *E, uint32_t key) {
+__device__ __forceinline__ const uint32_t *lds_first_above(const uint32_t *E, uint32_t key) {
     const uint32_t *p = E;   // stepping the address keeps each round to one add
 #pragma unroll
     for (uint32_t S = TILE / 2; S > 0; S >>= 1) p = p[S - 1] <= key ? p + S : p;
-    return uint32_t(p - E);
+    return p;
 }
 
 // the same search in two arrays at once (independent LDS reads overlap)
 template <int TILE>
-__device__ __forceinline__ void lds_rank2(const uint32_t *E1, const uint32_t *E2, uint32_t key, uint32_t &r1,
-                                          uint32_t &r2) {
+__device__ __forceinline__ void lds_first_above2(const uint32_t *E1, const uint32_t *E2, uint32_t key,
+                                                 const uint32_t *&p1, const uint32_t *&p2) {
     const uint32_t *p = E1, *q = E2;
 #pragma unroll
     for (uint32_t S = TILE / 2; S > 0; S >>= 1) {
@@ -133,37 +148,43 @@ __device__ __forceinline__ void lds_rank2(const uint32_t *E1, const uint32_t *E2
         p = u <= key ? p + S : p;
         q = v <= key ? q + S : q;
     }
-    r1 = uint32_t(p - E1);
-    r2 = uint32_t(q - E2);
+    p1 = p;
+    p2 = q;
 }
 
-// Copy X's A and F lists (na, nf < TILE intervals) into the resident arrays,
-// padding all TILE slots: every global load is issued before the first LDS
-// write, so the copy costs one memory round trip.
+// Copy X's A and F lists (na, nf < TILE intervals) into the resident arrays
+// and pad all TILE slots.  The copy goes from global memory straight into
+// LDS (no registers); every load is issued before the one wait, so the copy
+// costs one memory round trip.
+__device__ __forceinline__ void dma_dword(const uint32_t *src, uint32_t *lds_chunk) {
+    // lane l's word lands at lds_chunk[l]
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_chunk, 4, 0, 0);
+}
+
 template <int TILE>
 __device__ __forceinline__ void load_resident(const Resident &x, const uint32_t *__restrict__ as,
                                               const uint32_t *__restrict__ ae, uint32_t na,
                                               const uint32_t *__restrict__ fs, const uint32_t *__restrict__ fe,
                                               uint32_t nf, uint32_t lane) {
-    constexpr int R = TILE / 64;
-    uint32_t vas[R], vae[R], vfs[R], vfe[R];
-#pragma unroll
-    for (int i = 0; i < R; i++) {
+#pragma unroll 1
+    for (int i = 0; i < TILE / 64; i++) {
         const uint32_t t = i * 64 + lane;
-        const bool a = t < na, f = t < nf;
-        vas[i] = a ? as[t] : 0xffffffffu;
-        vae[i] = a ? ae[t] : 0xffffffffu;
-        vfs[i] = f ? fs[t] : 0xffffffffu;
-        vfe[i] = f ? fe[t] : 0xffffffffu;
+        if (t < na) {
+            dma_dword(as + t, x.as + i * 64);
+            dma_dword(ae + t, x.ae + i * 64);
+        } else {
+            x.as[t] = 0xffffffffu;
+            x.ae[t] = 0xffffffffu;
+        }
+        if (t < nf) {
+            dma_dword(fs + t, x.fs + i * 64);
+            dma_dword(fe + t, x.fe + i * 64);
+        } else {
+            x.fs[t] = 0xffffffffu;
+            x.fe[t] = 0xffffffffu;
+        }
     }
-#pragma unroll
-    for (int i = 0; i < R; i++) {
-        const uint32_t t = i * 64 + lane;
-        x.as[t] = vas[i];
-        x.ae[t] = vae[i];
-        x.fs[t] = vfs[i];
-        x.fe[t] = vfe[i];
-    }
+    __builtin_amdgcn_s_waitcnt(0);   // the copies have landed in LDS
 }
 
 // Stream Y[j..m) (sorted, disjoint) against the resident A-list until an
@@ -179,10 +200,10 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
         uint32_t s[C], e[C];
 #pragma unroll
         for (int c = 0; c < C; c++) {
-            const uint32_t k = j + c * 64 + lane;
-            const bool v = k < m;
-            s[c] = v ? ys[k] : 0u;   // idle lanes: an empty [0, 0) element
-            e[c] = v ? ye[k] : 0u;
+            // lanes past the end read the last element and take it as empty
+            const uint32_t k = j + c * 64 + lane, kk = min(k, m - 1);
+            s[c] = gload(ys, kk);
+            e[c] = k < m ? gload(ye, kk) : 0u;
         }
         // this chunk and all later ones start at or after the piece's end
         if (uniform(s[0]) >= stop) break;
@@ -192,14 +213,14 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
             if (FA) {
                 // the F search runs beside the A search; its answer counts
                 // only where the element overlaps the A-list
-                uint32_t pa, pf;
-                lds_rank2<TILE>(x.ae, x.fe, s[c], pa, pf);
-                const uint32_t sa = x.as[pa], sf = x.fs[pf];
+                const uint32_t *pa, *pf;
+                lds_first_above2<TILE>(x.ae, x.fe, s[c], pa, pf);
+                const uint32_t sa = pa[TILE], sf = pf[TILE];
                 const bool h = sa < e[c];
                 hit |= h;
                 f |= h & (sf < e[c]);
             } else {
-                hit |= x.as[lds_rank<TILE>(x.ae, s[c])] < e[c];
+                hit |= lds_first_above<TILE>(x.ae, s[c])[TILE] < e[c];
             }
         }
         if (__any(hit)) {
@@ -291,7 +312,8 @@ __device__ __forceinline__ const uint32_t *lane_ptr(const uint32_t *p, uint32_t 
 }
 
 // One pair's lists with X = S's object when `xs`, else R's.
-__device__ __forceinline__ PairLists pair_lists(const FilterArgs &a, bool xs, uint64_t ar0, uint32_t nar,
+template <class Args>
+__device__ __forceinline__ PairLists pair_lists(const Args &a, bool xs, uint64_t ar0, uint32_t nar,
                                                 uint64_t fr0, uint32_t nfr, uint64_t as0, uint32_t nas,
                                                 uint64_t fs0, uint32_t nfs) {
     PairLists L;
@@ -321,10 +343,10 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
     const uint32_t w = uniform(threadIdx.x >> 6);
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
     Resident res;
-    res.as = lds_words + w * 4 * TILE;
-    res.ae = res.as + TILE;
-    res.fs = res.ae + TILE;
-    res.fe = res.fs + TILE;
+    res.ae = lds_words + w * 4 * TILE;   // layout: A.end, A.start, F.end, F.start
+    res.as = res.ae + TILE;
+    res.fe = res.as + TILE;
+    res.fs = res.fe + TILE;
     res.na = res.nf = 0;
     uint32_t cached = kNone;   // resident object id | side bit
 
@@ -340,9 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
             // The arguments are read afresh for every grab (through a pointer
             // the compiler cannot see through), so they hold no scalar
             // registers while the grab's pairs are processed.
-            const BatchArgs *pb = &b;
+            typedef const __attribute__((address_space(4))) BatchArgs *KArgs;
+            KArgs pb = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
             asm volatile("" : "+s"(pb));
-            const FilterArgs &a = pb->f;
+            const __attribute__((address_space(4))) FilterArgs &a = pb->f;
             unsigned int got = 0;
             if (lane == 0) got = atomicAdd(&pb->xhead[seg], grab);
             const uint64_t g0 = lo + uniform(__shfl(got, 0));
@@ -358,12 +381,14 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
             PairLists m{};
             uint32_t key = kNone;
             if (p < g1) {
-                const uint32_t r = a.r[p], s = a.s[p];
+                const uint32_t r = gload32(a.r, p), s = gload32(a.s, p);
                 if (r < a.n_r && s < a.n_s) {
-                    const uint64_t ar0 = a.Ar.off[r], fr0 = a.Fr.off[r];
-                    const uint64_t as0 = a.As.off[s], fs0 = a.Fs.off[s];
-                    const uint32_t nar = uint32_t(a.Ar.off[r + 1] - ar0), nfr = uint32_t(a.Fr.off[r + 1] - fr0);
-                    const uint32_t nas = uint32_t(a.As.off[s + 1] - as0), nfs = uint32_t(a.Fs.off[s + 1] - fs0);
+                    const uint64_t ar0 = gload64(a.Ar.off, r), fr0 = gload64(a.Fr.off, r);
+                    const uint64_t as0 = gload64(a.As.off, s), fs0 = gload64(a.Fs.off, s);
+                    const uint32_t nar = uint32_t(gload64(a.Ar.off, r + 1) - ar0);
+                    const uint32_t nfr = uint32_t(gload64(a.Fr.off, r + 1) - fr0);
+                    const uint32_t nas = uint32_t(gload64(a.As.off, s + 1) - as0);
+                    const uint32_t nfs = uint32_t(gload64(a.Fs.off, s + 1) - fs0);
                     const uint32_t mr = max(nar, nfr), ms = max(nas, nfs);
                     // R resident when its lists fit a tile; else S when its
                     // do or when neither does and S's are shorter

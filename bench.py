@@ -52,6 +52,14 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times (reference dispatches for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="served selection queries instead of the batch filter (own JSON line)")
+    ap.add_argument("--serve-objects", type=int, default=1_000_000)
+    ap.add_argument("--partitioned", action="store_true",
+                    help="partitioned join, raw and compressed lists (own JSON line)")
+    ap.add_argument("--part-objects", type=int, default=500_000)
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="offered arrivals per load level last about this long (at most 10^4 queries)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
 
@@ -91,6 +99,166 @@ def cpu_baseline(R, S, g, seconds):
                        "not timed")}
 
 
+def serve_bench(args):
+    """Served selection queries on one GPU: S device-resident, queries built
+    on host threads, filtered in continuous batches.  Saturation throughput
+    (all queries offered at once), then Poisson arrivals at 0.5, 0.8 and
+    0.95 of it; per level p50/p99 of submit-to-done latency (the library's
+    steady clock), of its host list-build part, and pairs/s."""
+    import torch
+
+    import synth
+    from paper_2307_01716_amd import april
+
+    assert torch.cuda.is_available(), "no HIP device"
+    t0 = time.time()
+    S, Q, g = synth.configs.serving(n_s=args.serve_objects, n_queries=11_000)
+    log(f"generated S={len(S)} queries={len(Q)} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
+    dS = april.april_lists_to_device(hS)
+    torch.cuda.synchronize()
+    info = hS.info()
+    log(f"S lists: A={info.n_a} F={info.n_f} intervals, built and uploaded in {time.time() - t0:.1f}s")
+    srv = april.Server(dS, S.mbrs())
+    warm, n_sat = 1000, 4000
+    nq = len(Q)
+
+    def collect(tickets):
+        out = []
+        for t in tickets:
+            out.append(srv.wait(t, 600))
+            srv.release(t)
+        return out
+
+    collect([srv.submit(Q.polygon(k)) for k in range(warm)])
+    log(f"warm-up: {warm} queries")
+    t0 = time.perf_counter()
+    res = collect([srv.submit(Q.polygon(warm + k)) for k in range(n_sat)])
+    t_sat = time.perf_counter() - t0
+    sat_qps = n_sat / t_sat
+    sat_pairs = sum(len(r.s_ids) for r in res)
+    log(f"saturation: {n_sat} queries in {t_sat:.2f}s = {sat_qps:.0f} queries/s, "
+        f"{sat_pairs / t_sat / 1e6:.1f} M pairs/s, {sat_pairs / n_sat:.0f} pairs/query")
+    rng = np.random.default_rng(7)
+    levels = []
+    nxt = warm + n_sat
+    for load in (0.5, 0.8, 0.95):
+        rate = load * sat_qps
+        n = int(min(10_000, max(200, rate * args.serve_seconds)))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+        tickets = []
+        t0 = time.perf_counter()
+        for k in range(n):
+            while time.perf_counter() - t0 < arrivals[k]:
+                pass
+            tickets.append(srv.submit(Q.polygon((nxt + k) % nq)))
+        res = collect(tickets)
+        wall = time.perf_counter() - t0
+        nxt += n
+        lat = np.array([r.t_done - r.t_submit for r in res]) * 1e3
+        bld = np.array([r.t_built - r.t_submit for r in res]) * 1e3
+        pairs = sum(len(r.s_ids) for r in res)
+        lv = {"load": load, "queries": n, "offered_qps": rate, "achieved_qps": n / wall,
+              "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+              "build_p50_ms": float(np.percentile(bld, 50)), "build_p99_ms": float(np.percentile(bld, 99)),
+              "pairs_per_s": pairs / wall, "pairs_per_query": pairs / n}
+        levels.append(lv)
+        log(f"load {load}: {n} queries at {rate:.0f}/s offered: latency p50 {lv['p50_ms']:.2f} ms "
+            f"p99 {lv['p99_ms']:.2f} ms (lists built p50 {lv['build_p50_ms']:.2f} ms, "
+            f"p99 {lv['build_p99_ms']:.2f} ms); {lv['pairs_per_s'] / 1e6:.1f} M pairs/s")
+    st = srv.stats()
+    srv.close()
+    out = {"metric": "served selection queries (p50/p99 latency per offered load)",
+           "value": sat_pairs / t_sat, "unit": "pairs/s", "n_gpus": 1, "steps": len(levels),
+           "warmup": warm, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"served: S = {len(S)} star polygons device-resident, grid 2^16; "
+                                  "queries 10..10^4 vertices, radius 5e-4..0.05 (log-uniform)",
+                      "slots": st["slots"], "cap_pairs": st["cap_pairs"]},
+           "served": {"saturation_qps": sat_qps, "saturation_pairs_per_s": sat_pairs / t_sat,
+                      "levels": levels}}
+    print(json.dumps(out), flush=True)
+
+
+def partitioned_bench(args):
+    """Partitioned join on one GPU: |R| = |S| = n at-scale polygons, the unit
+    square cut into 16 x 16 partitions with a grid of order 16 each, every
+    object an instance in each partition its MBR meets, pairs kept in the
+    partition holding their reference point.  The same pairs are filtered on
+    raw and on delta + VByte lists (batched schedule, one launch over all
+    partitions); HIP events time each launch."""
+    import torch
+
+    import synth
+    from paper_2307_01716_amd import april, partitioned, tune
+
+    assert torch.cuda.is_available(), "no HIP device"
+    t0 = time.time()
+    R, S, lay = synth.configs.partitioned(n=args.part_objects)
+    log(f"generated R={len(R)} S={len(S)}, {lay.k}x{lay.k} partitions, "
+        f"{len(lay.r_obj)} + {len(lay.s_obj)} instances in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    hR = partitioned.build_instances(lay, R, "r")
+    hS = partitioned.build_instances(lay, S, "s")
+    log(f"built instance lists in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    r_np, s_np, n_all = partitioned.pairs(lay, R, S, with_all_count=True)
+    P = len(r_np)
+    log(f"pairs: {P} after the reference-point rule, {n_all} partition-local before "
+        f"({time.time() - t0:.1f}s)")
+    stream = torch.cuda.current_stream()
+    r = torch.from_numpy(r_np.view(np.int32)).cuda()
+    s = torch.from_numpy(s_np.view(np.int32)).cuda()
+    verdict = torch.empty(P, dtype=torch.uint8, device="cuda")
+    counts = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
+    forms, ref = {}, None
+    for codec, name, grid in ((april.CODEC_RAW, "raw", {"tile": (256, 512), "chunk": (1, 2)}),
+                              (april.CODEC_VBYTE, "vbyte", {"tile": (256, 512, 1024),
+                                                            "search_min": (1024, 4096)})):
+        dR = april.april_lists_to_device(hR, codec=codec, stream=stream)
+        dS = april.april_lists_to_device(hS, codec=codec, stream=stream)
+        torch.cuda.synchronize()
+        nbytes = dR.info().device_bytes + dS.info().device_bytes
+        best = None
+        for vals in __import__("itertools").product(*grid.values()):
+            cfg = dict(zip(grid, vals))
+            ms = tune.time_config(dR, dS, r, s, verdict, counts, ws, reps=5, **cfg)
+            log(f"  {name} {cfg}: {ms:.3f} ms")
+            if best is None or ms < best[1]:
+                best = (cfg, ms)
+        cfg, _ = best
+        ms = tune.time_config(dR, dS, r, s, verdict, counts, ws, reps=args.steps, **cfg)
+        c = counts.cpu().numpy()
+        if ref is None:
+            ref = verdict.clone()
+        assert torch.equal(verdict, ref), "raw and compressed verdicts differ"
+        forms[name] = {"kernel_ms": ms, "pairs_per_s": P / (ms / 1e3), "device_bytes": int(nbytes),
+                       "tuning": cfg, "verdicts": {"TN": int(c[0]), "TH": int(c[1]), "IND": int(c[2])}}
+        if codec == april.CODEC_RAW:
+            by = torch.empty(P, dtype=torch.int64, device="cuda")
+            april.april_alg2_bytes(dR, dS, r, s, by, stream=stream)
+            torch.cuda.synchronize()
+            forms[name]["alg_bytes"] = int(by.sum().item())
+            forms[name]["alg_GBps"] = forms[name]["alg_bytes"] / (ms / 1e3) / 1e9
+            del by
+        log(f"{name}: {ms:.3f} ms, {P / ms / 1e6:.3f} G pairs/s, lists {nbytes / 1e9:.2f} GB on device")
+        del dR, dS
+        torch.cuda.synchronize()
+    out = {"metric": "candidate pairs filtered/s (partitioned join, delta + VByte lists decoded in-kernel)",
+           "value": forms["vbyte"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": forms["vbyte"]["kernel_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"partitioned: {len(R)} x {len(S)} star polygons, {lay.k}x{lay.k} "
+                                  "partitions, grid 2^16 each",
+                      "pairs": P, "pairs_before_dedup": int(n_all),
+                      "instances": [int(len(lay.r_obj)), int(len(lay.s_obj))]},
+           "forms": forms,
+           "compression": forms["raw"]["device_bytes"] / forms["vbyte"]["device_bytes"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -98,6 +266,12 @@ def main():
               "(the filter runs on a single MI355X; see the design notes on sharding)",
               file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
+    if args.partitioned:
+        partitioned_bench(args)
+        return
     import torch
 
     import synth

@@ -1,11 +1,13 @@
 // Host/device list containers, errors, grid checks, Hilbert numbering,
 // device info and the host MBR join.
 #include <hip/hip_runtime_api.h>
+#include <sched.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <mutex>
+#include <thread>
 
 #include "internal.hpp"
 
@@ -19,11 +21,19 @@ int fail(int code, const std::string &msg) {
 }
 void clear_error() { g_last_error.clear(); }
 
+// Host worker threads: APRIL_HOST_THREADS if set, else the CPUs this
+// process may run on, capped by OMP_NUM_THREADS when that is set, and by 64.
 int host_threads() {
-    unsigned n = std::thread::hardware_concurrency();
     const char *e = getenv("APRIL_HOST_THREADS");
     if (e && atoi(e) > 0) return atoi(e);
-    return n ? (int)std::min(n, 64u) : 4;
+    int n = 0;
+    cpu_set_t set;
+    if (sched_getaffinity(0, sizeof set, &set) == 0) n = CPU_COUNT(&set);
+    if (n <= 0) n = int(std::thread::hardware_concurrency());
+    if (n <= 0) n = 4;
+    const char *omp = getenv("OMP_NUM_THREADS");
+    if (omp && atoi(omp) > 0) n = std::min(n, atoi(omp));
+    return std::min(n, 64);
 }
 
 bool same_grid(const april_grid_t &a, const april_grid_t &b) {

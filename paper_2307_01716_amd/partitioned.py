@@ -32,10 +32,14 @@ def build_instances(layout, polys, side: str, flags=april.STRICT) -> april.Lists
     return april.Lists(h.value)
 
 
-def pairs(layout, R, S):
-    """Partition-local candidate pairs as instance indices (r_inst, s_inst)."""
+def pairs(layout, R, S, with_all_count: bool = False):
+    """Partition-local candidate pairs as instance indices (r_inst, s_inst);
+    with `with_all_count` also the number of partition-local MBR pairs
+    before the reference-point rule (each global pair once per partition
+    both MBRs meet)."""
     mR, mS = R.mbrs(), S.mbrs()
     out_r, out_s = [], []
+    n_all = 0
     for p in range(layout.k * layout.k):
         r0, r1 = int(layout.r_off[p]), int(layout.r_off[p + 1])
         s0, s1 = int(layout.s_off[p]), int(layout.s_off[p + 1])
@@ -43,10 +47,11 @@ def pairs(layout, R, S):
             continue
         br, bs = mR[layout.r_obj[r0:r1]], mS[layout.s_obj[s0:s1]]
         i, j = april.april_mbr_join(br, bs)
+        n_all += len(i)
         # reference point: lower-left corner of the MBR intersection
         keep = layout.part_of_point(np.maximum(br[i, 0], bs[j, 0]), np.maximum(br[i, 1], bs[j, 1])) == p
         out_r.append(i[keep].astype(np.uint64) + r0)
         out_s.append(j[keep].astype(np.uint64) + s0)
     r = np.concatenate(out_r).astype(np.uint32) if out_r else np.zeros(0, np.uint32)
     s = np.concatenate(out_s).astype(np.uint32) if out_s else np.zeros(0, np.uint32)
-    return r, s
+    return (r, s, n_all) if with_all_count else (r, s)

@@ -368,8 +368,11 @@ def main():
         elif not args.no_tune:
             t0 = time.time()
             cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3, log=log)
+            dflt_ms = tune.time_config(dR, dS, r, s, verdict, counts, ws, reps=3)
             log(f"autotune: {len(table)} settings in {time.time() - t0:.1f}s; best {cfg} "
-                f"({best_ms:.3f} ms)")
+                f"({best_ms:.3f} ms); library defaults {dflt_ms:.3f} ms")
+            if best_ms > 0.99 * dflt_ms:   # not clearly better: keep the defaults
+                cfg = {}
             kw = tune.call_config(cfg)
 
         def batched_eager():
@@ -402,6 +405,16 @@ def main():
 
     main_form = "batched" if "batched" in forms else "plain"
     f = forms[main_form]
+    # HBM traffic per launch from the committed rocprofv3 counters, when they
+    # were taken on this kernel's current sources with this configuration
+    from paper_2307_01716_amd import profiling
+    kname = "k_batched" if main_form == "batched" else "k_filter_plain"
+    tr_cfg = f.get("tuning", {}) if main_form == "batched" else {}
+    traffic = profiling.read_traffic(os.path.join(HERE, "profiles", f"{kname}_scale200k_traffic.txt"),
+                                     kname, tr_cfg, P)
+    if "plain" in forms:
+        forms["plain"]["traffic_bytes"] = profiling.read_traffic(
+            os.path.join(HERE, "profiles", "k_filter_plain_scale200k_traffic.txt"), "k_filter_plain", {}, P)
     out = {
         "metric": "candidate pairs filtered/s (" + (
             "batched persistent schedule, hipGraph replay" if main_form == "batched"
@@ -422,7 +435,7 @@ def main():
         "forms": forms,
         "alg_bytes_per_launch": alg_bytes,
         "roofline": {"bound": "hbm", "achieved": f["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": f["alg_GBps"] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": f["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic},
     }
     if not args.no_cpu_baseline:
         t0 = time.time()

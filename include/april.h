@@ -182,7 +182,7 @@ typedef struct {
     uint32_t waves;        /* resident wavefronts (0 = library default) */
     uint32_t tile;         /* batched: intervals per list kept in LDS per wavefront:
                               128, 256 or 512 (0 = 512; compressed lists: 256, 512, 1024) */
-    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 1) */
+    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2) */
     uint32_t thread_max;   /* batched: pairs whose four lists all have at most this many
                               intervals run one lane per pair (0 = 8) */
     uint32_t search_min;   /* batched: streamed lists longer than this are first narrowed

@@ -458,7 +458,10 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
         APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_batched<TILE, C>, kBlock, 0));
         per_cu = q < 1 ? 1 : q;
     }
-    uint64_t blocks = uint64_t(cus) * per_cu;
+    // default residency (measured on the at-scale join): 4 waves per SIMD
+    // with 512-interval tiles, 6 with 256, as many as fit with 128
+    const int dflt = TILE >= 512 ? 4 : TILE >= 256 ? 6 : per_cu;
+    uint64_t blocks = uint64_t(cus) * std::min(per_cu, dflt);
     if (waves) blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
     // a range is near its end once its waves have about two full grabs each left
     BatchArgs bb = b;
@@ -487,7 +490,7 @@ int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? cus / 32 : 1; }
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
                    hipStream_t stream) {
     const uint32_t tile = o.tile ? o.tile : 512;
-    const uint32_t chunk = o.chunk ? o.chunk : 1;
+    const uint32_t chunk = o.chunk ? o.chunk : 2;
     BatchArgs b;
     b.f = a;
     b.xhead = static_cast<unsigned int *>(workspace);

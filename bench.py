@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times (reference dispatches for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["scale", "skewed"], default="scale",
+                    help="scale: 200k x 200k polygons (default); skewed: the same plus 2000 "
+                         "complex polygons (20k-100k vertices) per side")
     ap.add_argument("--serve", action="store_true",
                     help="served selection queries instead of the batch filter (own JSON line)")
     ap.add_argument("--serve-objects", type=int, default=1_000_000)
@@ -282,7 +285,7 @@ def main():
     log(f"device: {dev['name']} {dev['arch']} CUs={dev['compute_units']}")
 
     t0 = time.time()
-    R, S, g = synth.configs.scale()
+    R, S, g = synth.configs.scale() if args.workload == "scale" else synth.configs.skewed()
     log(f"generated R={len(R)} S={len(S)} in {time.time() - t0:.1f}s")
     t0 = time.time()
     hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
@@ -411,7 +414,7 @@ def main():
     kname = "k_batched" if main_form == "batched" else "k_filter_plain"
     tr_cfg = f.get("tuning", {}) if main_form == "batched" else {}
     traffic = profiling.read_traffic(os.path.join(HERE, "profiles", f"{kname}_scale200k_traffic.txt"),
-                                     kname, tr_cfg, P)
+                                     kname, tr_cfg, P) if args.workload == "scale" else None
     if "plain" in forms:
         forms["plain"]["traffic_bytes"] = profiling.read_traffic(
             os.path.join(HERE, "profiles", "k_filter_plain_scale200k_traffic.txt"), "k_filter_plain", {}, P)
@@ -430,14 +433,19 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "scale: 200k x 200k star polygons, grid 2^16, all MBR candidate pairs",
+        "config": {"workload": ("scale: 200k x 200k star polygons, grid 2^16, all MBR candidate pairs"
+                                if args.workload == "scale" else
+                                "skewed: 200k x 200k star polygons plus 2000 x 2000 with 20k-100k vertices "
+                                "(radius 0.02-0.1), grid 2^16, all MBR candidate pairs"),
                    "pairs": P, "schedule": main_form, "verdicts": f["verdicts"]},
         "forms": forms,
         "alg_bytes_per_launch": alg_bytes,
         "roofline": {"bound": "hbm", "achieved": f["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": f["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic},
     }
-    if not args.no_cpu_baseline:
+    # the oracle's brute-force list builder cannot sample the skewed workload
+    # (its large polygons cover up to 10^8 cells each)
+    if not args.no_cpu_baseline and args.workload == "scale":
         t0 = time.time()
         out["cpu_baseline"] = cpu_baseline(R, S, g, args.cpu_seconds)
         log(f"cpu baseline: {out['cpu_baseline']['value'] / 1e6:.2f} M pairs/s "

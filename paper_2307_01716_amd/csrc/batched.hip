@@ -108,8 +108,8 @@ __device__ uint32_t wave_first_above(const uint32_t *__restrict__ v, uint32_t m,
         const uint64_t f = __builtin_ctzll(mask);
         const uint64_t pf = lo + (f + 1) * step - 1;
         const uint32_t nlo = uint32_t(lo + f * step);
-        hi = pf < hi ? uint32_t(pf) : hi;
-        lo = nlo;
+        hi = uniform(pf < hi ? uint32_t(pf) : hi);
+        lo = uniform(nlo);
     }
     if (hi - lo == 0) return lo;
     const uint32_t j = lo + lane;
@@ -242,58 +242,73 @@ struct PairLists {
     uint32_t nxa, nxf, nya, nyf;
 };
 
-// Alg. 2's verdict for one pair, by the whole wave.  X is loaded piece by
-// piece (one piece when both its lists are shorter than TILE; that piece
-// stays resident for the next pair with the same `key`).
+// Joins of one resident piece (key range [k0, k1)) with the streamed lists:
+// 0 = no AA overlap, 1 = a true hit (FA or AF overlap), 2 = AA overlap only.
+// Every value here is wave-uniform; uniform() says so to the compiler.
 template <int TILE, int C>
-__device__ uint8_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, const PairLists &L,
-                             uint32_t search_min, uint32_t lane) {
+__device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLists &L, uint32_t k0, uint32_t k1,
+                                               uint32_t search_min, uint32_t lane) {
+    // Y elements that can meet this piece: end above x_lo, start below x_hi
+    const uint32_t x_lo = max(k0, uniform(res.as[0]));
+    const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
+    const bool narrow = k0 > 0;
+    bool th = false;
+    const uint32_t ja = (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, x_lo, lane)) : 0;
+    if (!stream_piece<TILE, C, true>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th)) return 0;
+    if (th) return 1;
+    const uint32_t jf = (narrow || L.nyf > search_min) ? uniform(wave_first_above(L.yfe, L.nyf, x_lo, lane)) : 0;
+    return stream_piece<TILE, C, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th) ? 1 : 2;
+}
+
+// Alg. 2's verdict for one pair, by the whole wave.  When both of X's lists
+// are shorter than TILE they are one piece, kept resident for the next pair
+// with the same `key`; otherwise X is loaded piece by piece.
+template <int TILE, int C>
+__device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, const PairLists &L,
+                              uint32_t search_min, uint32_t lane) {
     if (L.nxa == 0 || L.nya == 0) return APRIL_TN;
-    const bool one = L.nxa < TILE && L.nxf < TILE;
+    if (L.nxa < TILE && L.nxf < TILE) {
+        if (key != cached) {
+            wave_lds_sync();
+            load_resident<TILE>(res, L.xas, L.xae, L.nxa, L.xfs, L.xfe, L.nxf, lane);
+            wave_lds_sync();
+            res.na = L.nxa;
+            res.nf = L.nxf;
+            cached = key;
+        }
+        const uint32_t j = join_piece<TILE, C>(res, L, 0, kNone, search_min, lane);
+        return j == 0 ? APRIL_TN : j == 1 ? APRIL_TH : APRIL_INDECISIVE;
+    }
+    cached = kNone;
     bool aa = false;
     uint32_t a0 = 0, f0 = 0, k0 = 0;
     for (;;) {
+        // at most TILE - 1 A elements from a0; the range ends where the next
+        // one starts; then at most TILE - 1 F elements
         uint32_t a1 = L.nxa, f1 = L.nxf, k1 = kNone;
-        if (!one) {
-            // at most TILE - 1 A elements from a0; the range ends where the
-            // next one starts; then at most TILE - 1 F elements
-            if (L.nxa - a0 > TILE - 1) {
-                a1 = a0 + TILE - 1;
-                k1 = L.xas[a1];
-                f1 = f0 + wave_first_above(L.xfs + f0, L.nxf - f0, k1 - 1, lane);
-            }
-            if (f1 - f0 > TILE - 1) {
-                f1 = f0 + TILE - 1;
-                k1 = L.xfs[f1];
-                a1 = a0 + wave_first_above(L.xas + a0, a1 - a0, k1 - 1, lane);
-            }
+        if (L.nxa - a0 > TILE - 1) {
+            a1 = a0 + TILE - 1;
+            k1 = uniform(gload(L.xas, a1));
+            f1 = f0 + uniform(wave_first_above(L.xfs + f0, L.nxf - f0, k1 - 1, lane));
         }
-        if (!one || key != cached) {
-            wave_lds_sync();
-            load_resident<TILE>(res, L.xas + a0, L.xae + a0, a1 - a0, L.xfs + f0, L.xfe + f0, f1 - f0, lane);
-            wave_lds_sync();
-            res.na = a1 - a0;
-            res.nf = f1 - f0;
-            cached = one ? key : kNone;
+        if (f1 - f0 > TILE - 1) {
+            f1 = f0 + TILE - 1;
+            k1 = uniform(gload(L.xfs, f1));
+            a1 = a0 + uniform(wave_first_above(L.xas + a0, a1 - a0, k1 - 1, lane));
         }
-        // Y elements that can meet this piece: end above x_lo, start below x_hi
-        const uint32_t x_lo = max(k0, uniform(res.as[0]));
-        const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
-        const bool narrow = k0 > 0;
-        bool th = false;
-        const uint32_t ja = (narrow || L.nya > search_min) ? wave_first_above(L.yae, L.nya, x_lo, lane) : 0;
-        if (stream_piece<TILE, C, true>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th)) {
-            if (th) return APRIL_TH;
-            aa = true;
-            const uint32_t jf = (narrow || L.nyf > search_min) ? wave_first_above(L.yfe, L.nyf, x_lo, lane) : 0;
-            if (stream_piece<TILE, C, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th))
-                return APRIL_TH;
-        }
+        wave_lds_sync();
+        load_resident<TILE>(res, L.xas + a0, L.xae + a0, a1 - a0, L.xfs + f0, L.xfe + f0, f1 - f0, lane);
+        wave_lds_sync();
+        res.na = a1 - a0;
+        res.nf = f1 - f0;
+        const uint32_t j = join_piece<TILE, C>(res, L, k0, k1, search_min, lane);
+        if (j == 1) return APRIL_TH;
+        aa |= j == 2;
         if (k1 == kNone) break;
         // next piece: the first elements that end above k1
         k0 = k1;
-        a0 = L.xae[a1 - 1] > k1 ? a1 - 1 : a1;
-        f0 = (f1 > 0 && L.xfe[f1 - 1] > k1) ? f1 - 1 : f1;
+        a0 = uniform(gload(L.xae, a1 - 1)) > k1 ? a1 - 1 : a1;
+        f0 = (f1 > 0 && uniform(gload(L.xfe, f1 - 1)) > k1) ? f1 - 1 : f1;
     }
     return aa ? APRIL_INDECISIVE : APRIL_TN;
 }

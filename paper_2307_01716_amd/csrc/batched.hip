@@ -200,10 +200,10 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
         uint32_t s[C], e[C];
 #pragma unroll
         for (int c = 0; c < C; c++) {
-            // lanes past the end read the last element and take it as empty
-            const uint32_t k = j + c * 64 + lane, kk = min(k, m - 1);
-            s[c] = gload(ys, kk);
-            e[c] = k < m ? gload(ye, kk) : 0u;
+            // lanes past the end load nothing and take an empty [0, 0)
+            const uint32_t k = j + c * 64 + lane;
+            s[c] = k < m ? gload(ys, k) : 0u;
+            e[c] = k < m ? gload(ye, k) : 0u;
         }
         // this chunk and all later ones start at or after the piece's end
         if (uniform(s[0]) >= stop) break;
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
             uint32_t key = kNone;
             if (p < g1) {
                 const uint32_t r = gload32(a.r, p), s = gload32(a.s, p);
-                if (r < a.n_r && s < a.n_s) {
+                if ((r < a.n_r) & (s < a.n_s)) {
                     const uint64_t ar0 = gload64(a.Ar.off, r), fr0 = gload64(a.Fr.off, r);
                     const uint64_t as0 = gload64(a.As.off, s), fs0 = gload64(a.Fs.off, s);
                     const uint32_t nar = uint32_t(gload64(a.Ar.off, r + 1) - ar0);

@@ -225,6 +225,8 @@ def partitioned_bench(args):
         torch.cuda.synchronize()
         nbytes = dR.info().device_bytes + dS.info().device_bytes
         best = None
+        if args.no_tune:   # fixed settings (as profiled): the library defaults
+            grid = {"tile": (512,)}
         for vals in __import__("itertools").product(*grid.values()):
             cfg = dict(zip(grid, vals))
             ms = tune.time_config(dR, dS, r, s, verdict, counts, ws, reps=5, **cfg)
@@ -273,6 +275,14 @@ def main():
         serve_bench(args)
         return
     if args.partitioned:
+        if args.copy_calibration:
+            import torch
+            src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         partitioned_bench(args)
         return
     import torch

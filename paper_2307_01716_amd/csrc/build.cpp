@@ -23,7 +23,9 @@
 //  Cells before the first and after the last touched id are outside: the
 //  curve starts and ends in the outer ring, which no polygon reaches.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 
 #include "internal.hpp"
 
@@ -55,12 +57,17 @@ public:
     void set_grid(const LatticeGrid &g) { g_ = g; }
 
     int run(const Poly &p, Result &out);
+    // the same lists, with the steps split over `threads` threads (for one
+    // large polygon)
+    int run_parallel(const Poly &p, Result &out, int threads);
 
 private:
-    void edge_cells(int64_t ax, int64_t ay, int64_t bx, int64_t by);
+    void edge_cells(int64_t ax, int64_t ay, int64_t bx, int64_t by, std::vector<uint64_t> &out) const;
+    void row_tables(const Poly &p, int threads = 1);
+    void intervalize(const uint8_t *cls, size_t m, Result &out) const;
     void edge_crossings(int64_t ax, int64_t ay, int64_t bx, int64_t by);
     bool centre_inside(uint32_t i, uint32_t j) const;
-    void push_f(uint64_t s, uint64_t e, std::vector<uint32_t> &f);
+    void push_f(uint64_t s, uint64_t e, std::vector<uint32_t> &f) const;
 
     LatticeGrid g_;
     std::vector<uint64_t> touched_;          // (hilbert id << 1) | interior crossed
@@ -68,10 +75,11 @@ private:
     std::vector<uint32_t> row_off_;          // CSR of crossings per row
     std::vector<int64_t> row_x_;             // floor of crossing x, doubled units
     std::vector<uint32_t> row_fill_;
+    std::vector<uint8_t> cls_;               // class bits per touched cell
 };
 
 // Cells met by the edge a-b, with the interior-crossed flag.
-void Builder::edge_cells(int64_t ax, int64_t ay, int64_t bx, int64_t by) {
+void Builder::edge_cells(int64_t ax, int64_t ay, int64_t bx, int64_t by, std::vector<uint64_t> &out) const {
     const int64_t w = g_.w;
     if (ay > by) { std::swap(ax, bx); std::swap(ay, by); }
     const bool horiz = (ay == by);
@@ -98,7 +106,7 @@ void Builder::edge_cells(int64_t ax, int64_t ay, int64_t bx, int64_t by) {
         if (open_row) { o0 = floor_div(n0, Dw); o1 = ceil_div(n1, Dw) - 1; }
         for (int64_t i = i0; i <= i1; i++) {
             const uint64_t d = hilbert_xy2d(g_.order, uint32_t(i), uint32_t(j));
-            touched_.push_back((d << 1) | uint64_t(i >= o0 && i <= o1));
+            out.push_back((d << 1) | uint64_t(i >= o0 && i <= o1));
         }
     }
 }
@@ -135,30 +143,16 @@ bool Builder::centre_inside(uint32_t i, uint32_t j) const {
     return (std::lower_bound(b, e, X) - b) & 1;
 }
 
-void Builder::push_f(uint64_t s, uint64_t e, std::vector<uint32_t> &f) {
+void Builder::push_f(uint64_t s, uint64_t e, std::vector<uint32_t> &f) const {
     if (!f.empty() && f.back() == s) f.back() = uint32_t(e);   // contiguous: extend
     else { f.push_back(uint32_t(s)); f.push_back(uint32_t(e)); }
 }
 
-int Builder::run(const Poly &p, Result &out) {
+// Centre-line crossing tables of every row the polygon spans.
+void Builder::row_tables(const Poly &p, int threads) {
     const size_t nv = p.x.size();
-    touched_.clear();
     int64_t ymin = p.y[0], ymax = p.y[0];
     for (size_t k = 0; k < nv; k++) { ymin = std::min(ymin, p.y[k]); ymax = std::max(ymax, p.y[k]); }
-    // 1. boundary cells
-    for (size_t k = 0; k < nv; k++) {
-        const size_t k2 = (k + 1 == nv) ? 0 : k + 1;
-        edge_cells(p.x[k], p.y[k], p.x[k2], p.y[k2]);
-    }
-    std::sort(touched_.begin(), touched_.end());
-    // merge duplicates: keep one entry per cell, interior flag ORed
-    size_t m = 0;
-    for (size_t t = 0; t < touched_.size(); t++) {
-        if (m && (touched_[m - 1] >> 1) == (touched_[t] >> 1)) touched_[m - 1] |= touched_[t] & 1;
-        else touched_[m++] = touched_[t];
-    }
-    touched_.resize(m);
-    // 2. centre-line crossings per row
     jmin_ = floor_div(ymin, g_.w) - 1;
     jmax_ = floor_div(ymax, g_.w) + 1;
     const size_t rows = size_t(jmax_ - jmin_ + 1);
@@ -181,8 +175,16 @@ int Builder::run(const Poly &p, Result &out) {
         const size_t k2 = (k + 1 == nv) ? 0 : k + 1;
         edge_crossings(p.x[k], p.y[k], p.x[k2], p.y[k2]);
     }
-    for (size_t r = 0; r < rows; r++) std::sort(row_x_.begin() + row_off_[r], row_x_.begin() + row_off_[r + 1]);
-    // 3. one-step intervalization
+    parallel(threads, [&](int t) {
+        for (size_t r = rows * size_t(t) / size_t(threads); r < rows * size_t(t + 1) / size_t(threads); r++)
+            std::sort(row_x_.begin() + row_off_[r], row_x_.begin() + row_off_[r + 1]);
+    });
+}
+
+// Classes of the sorted, merged touched cells (cls[t] bit 0: touched cell t is
+// Full, i.e. border-only contact with its centre inside; bit 1: the gap after
+// it is inside), turned into the A- and F-lists by one walk in Hilbert order.
+void Builder::intervalize(const uint8_t *cls, size_t m, Result &out) const {
     auto &A = out.a;
     auto &F = out.f;
     A.clear();
@@ -190,17 +192,12 @@ int Builder::run(const Poly &p, Result &out) {
     uint64_t a_start = touched_[0] >> 1;
     for (size_t t = 0; t < m; t++) {
         const uint64_t d = touched_[t] >> 1;
-        uint32_t ci, cj;
-        if (!(touched_[t] & 1)) {   // border-only contact: Full iff the centre is inside
-            hilbert_d2xy(g_.order, d, &ci, &cj);
-            if (centre_inside(ci, cj)) push_f(d, d + 1, F);
-        }
+        if (cls[t] & 1) push_f(d, d + 1, F);
         if (t + 1 == m) break;
         const uint64_t nxt = touched_[t + 1] >> 1;
         if (nxt == d + 1) continue;
         // gap [d+1, nxt): one class throughout
-        hilbert_d2xy(g_.order, d + 1, &ci, &cj);
-        if (centre_inside(ci, cj)) {
+        if (cls[t] & 2) {
             push_f(d + 1, nxt, F);
         } else {
             A.push_back(uint32_t(a_start));
@@ -210,8 +207,159 @@ int Builder::run(const Poly &p, Result &out) {
     }
     A.push_back(uint32_t(a_start));
     A.push_back(uint32_t((touched_[m - 1] >> 1) + 1));
+}
+
+// class bits of touched cell t (see intervalize)
+#define APRIL_CELL_CLASS(t, m)                                                              \
+    ([&](size_t t_) -> uint8_t {                                                            \
+        uint8_t c = 0;                                                                      \
+        uint32_t ci, cj;                                                                    \
+        const uint64_t d = touched_[t_] >> 1;                                               \
+        if (!(touched_[t_] & 1)) {                                                          \
+            hilbert_d2xy(g_.order, d, &ci, &cj);                                            \
+            if (centre_inside(ci, cj)) c |= 1;                                              \
+        }                                                                                   \
+        if (t_ + 1 < (m) && (touched_[t_ + 1] >> 1) != d + 1) {                             \
+            hilbert_d2xy(g_.order, d + 1, &ci, &cj);                                        \
+            if (centre_inside(ci, cj)) c |= 2;                                              \
+        }                                                                                   \
+        return c;                                                                           \
+    })(t)
+
+int Builder::run(const Poly &p, Result &out) {
+    const size_t nv = p.x.size();
+    touched_.clear();
+    // 1. boundary cells
+    for (size_t k = 0; k < nv; k++) {
+        const size_t k2 = (k + 1 == nv) ? 0 : k + 1;
+        edge_cells(p.x[k], p.y[k], p.x[k2], p.y[k2], touched_);
+    }
+    std::sort(touched_.begin(), touched_.end());
+    // merge duplicates: keep one entry per cell, interior flag ORed
+    size_t m = 0;
+    for (size_t t = 0; t < touched_.size(); t++) {
+        if (m && (touched_[m - 1] >> 1) == (touched_[t] >> 1)) touched_[m - 1] |= touched_[t] & 1;
+        else touched_[m++] = touched_[t];
+    }
+    touched_.resize(m);
+    // 2. centre-line crossings per row
+    row_tables(p);
+    // 3. one-step intervalization
+    cls_.resize(m);
+    for (size_t t = 0; t < m; t++) cls_[t] = APRIL_CELL_CLASS(t, m);
+    intervalize(cls_.data(), m, out);
     return APRIL_OK;
 }
+
+int Builder::run_parallel(const Poly &p, Result &out, int T) {
+    const size_t nv = p.x.size();
+    // 1. boundary cells, edges split over the threads
+    std::vector<std::vector<uint64_t>> part(T);
+    parallel(T, [&](int t) {
+        const size_t k0 = nv * size_t(t) / size_t(T), k1 = nv * size_t(t + 1) / size_t(T);
+        for (size_t k = k0; k < k1; k++) {
+            const size_t k2 = (k + 1 == nv) ? 0 : k + 1;
+            edge_cells(p.x[k], p.y[k], p.x[k2], p.y[k2], part[t]);
+        }
+    });
+    // 2. sample sort by cell id: T - 1 splitters from evenly spaced samples
+    //    of every part; each part is cut into the T id ranges, and range b
+    //    (bucket b) is gathered, sorted and merged by thread b
+    std::vector<uint64_t> sample;
+    for (int t = 0; t < T; t++)
+        for (size_t q = 1; q <= 32 && !part[t].empty(); q++) sample.push_back(part[t][part[t].size() * q / 33] >> 1);
+    std::sort(sample.begin(), sample.end());
+    std::vector<uint64_t> spl(T, 0);   // bucket b holds ids in [spl[b], spl[b + 1])
+    for (int b = 1; b < T; b++) spl[b] = sample.empty() ? 0 : sample[sample.size() * size_t(b) / size_t(T)];
+    auto bucket_of = [&](uint64_t key) {
+        return int(std::upper_bound(spl.begin() + 1, spl.end(), key >> 1) - spl.begin()) - 1;
+    };
+    std::vector<std::vector<size_t>> cnt(T, std::vector<size_t>(T + 1, 0));   // [part][bucket]
+    parallel(T, [&](int t) {
+        for (uint64_t v : part[t]) cnt[t][bucket_of(v) + 1]++;
+        for (int b = 0; b < T; b++) cnt[t][b + 1] += cnt[t][b];
+        // counting sort of the part by bucket (stable, in place via a copy)
+        std::vector<uint64_t> tmp(part[t].size());
+        std::vector<size_t> pos(cnt[t].begin(), cnt[t].end() - 1);
+        for (uint64_t v : part[t]) tmp[pos[bucket_of(v)]++] = v;
+        part[t].swap(tmp);
+    });
+    std::vector<std::vector<uint64_t>> bucket(T);
+    parallel(T, [&](int b) {
+        auto &v = bucket[b];
+        size_t n = 0;
+        for (int t = 0; t < T; t++) n += cnt[t][b + 1] - cnt[t][b];
+        v.reserve(n);
+        for (int t = 0; t < T; t++) v.insert(v.end(), part[t].begin() + cnt[t][b], part[t].begin() + cnt[t][b + 1]);
+        std::sort(v.begin(), v.end());
+        size_t m = 0;
+        for (size_t t = 0; t < v.size(); t++) {
+            if (m && (v[m - 1] >> 1) == (v[t] >> 1)) v[m - 1] |= v[t] & 1;
+            else v[m++] = v[t];
+        }
+        v.resize(m);
+    });
+    part.clear();
+    std::vector<size_t> boff(T + 1, 0);
+    for (int b = 0; b < T; b++) boff[b + 1] = boff[b] + bucket[b].size();
+    const size_t m = boff[T];
+    touched_.resize(m);
+    parallel(T, [&](int b) {
+        std::copy(bucket[b].begin(), bucket[b].end(), touched_.begin() + boff[b]);
+        std::vector<uint64_t>().swap(bucket[b]);
+    });
+    // 3. row tables, every cell's classes, then the walk, each split over
+    //    the threads; the walk's segments are stitched at their ends
+    row_tables(p, T);
+    cls_.resize(m);
+    std::vector<Result> seg(T);
+    std::vector<uint64_t> first_start(T), last_start(T);   // first A interval's start slot; carried a_start
+    std::vector<char> emitted(T, 0);
+    parallel(T, [&](int t) {
+        const size_t t0 = m * size_t(t) / size_t(T), t1 = m * size_t(t + 1) / size_t(T);
+        for (size_t i = t0; i < t1; i++) cls_[i] = APRIL_CELL_CLASS(i, m);
+        // walk [t0, t1): A intervals whose start is not yet known use the
+        // carried start of the segments before (filled in below)
+        auto &A = seg[t].a;
+        auto &F = seg[t].f;
+        uint64_t a_start = t0 < t1 ? touched_[t0] >> 1 : 0;
+        bool open = true;   // the current A interval started before this segment
+        for (size_t i = t0; i < t1; i++) {
+            const uint64_t d = touched_[i] >> 1;
+            if (cls_[i] & 1) push_f(d, d + 1, F);
+            if (i + 1 == m) break;
+            const uint64_t nxt = touched_[i + 1] >> 1;
+            if (nxt == d + 1) continue;
+            if (cls_[i] & 2) {
+                push_f(d + 1, nxt, F);
+            } else {
+                if (open) { emitted[t] = 1; first_start[t] = 0; }
+                A.push_back(open ? 0u : uint32_t(a_start));
+                A.push_back(uint32_t(d + 1));
+                a_start = nxt;
+                open = false;
+            }
+        }
+        last_start[t] = open ? ~uint64_t(0) : a_start;
+    });
+    auto &A = out.a;
+    auto &F = out.f;
+    A.clear();
+    F.clear();
+    uint64_t carry = touched_[0] >> 1;
+    for (int t = 0; t < T; t++) {
+        auto &a = seg[t].a;
+        if (emitted[t]) a[0] = uint32_t(carry);   // the interval open at the segment's start
+        A.insert(A.end(), a.begin(), a.end());
+        if (last_start[t] != ~uint64_t(0)) carry = last_start[t];
+        for (size_t k = 0; k < seg[t].f.size(); k += 2) push_f(seg[t].f[k], seg[t].f[k + 1], F);
+    }
+    A.push_back(uint32_t(carry));
+    A.push_back(uint32_t((touched_[m - 1] >> 1) + 1));
+    return APRIL_OK;
+}
+
+#undef APRIL_CELL_CLASS
 
 }  // namespace
 }  // namespace april
@@ -224,14 +372,19 @@ namespace {
 template <class GridOf>
 int build_collection(const std::vector<LatticeGrid> &lg, GridOf gid, const april_grid_t &desc,
                      uint64_t key, const double *xy, const uint64_t *vtx_off, uint64_t n, uint32_t flags,
-                     april_lists_t **out) {
+                     april_lists_t **out, int max_threads) {
     for (uint64_t k = 0; k < n; k++)
         if (vtx_off[k + 1] < vtx_off[k] + 3) return fail(APRIL_E_INVALID, "polygon with < 3 vertices");
     const bool strict = flags & APRIL_STRICT;
     std::vector<Result> res(n);
     std::atomic<uint64_t> next{0};
     std::atomic<int> err{0};
-    const int T = int(std::min<uint64_t>(host_threads(), n));
+    const int T = int(std::min<uint64_t>(std::max(1, max_threads), n));
+    // with fewer polygons than threads, a large polygon is built by several
+    // threads (about this many boundary cells or more: APRIL_PAR_BUILD_CELLS)
+    const int inner = std::max(1, max_threads / std::max(1, T));
+    const char *pe = getenv("APRIL_PAR_BUILD_CELLS");
+    const double par_cells = pe ? atof(pe) : 65536.0;
     parallel(T, [&](int) {
         Builder b(lg[0]);
         Poly p;
@@ -269,7 +422,15 @@ int build_collection(const std::vector<LatticeGrid> &lg, GridOf gid, const april
                 p.y.pop_back();
             }
             if (rc == APRIL_OK && p.x.size() < 3) rc = APRIL_E_INVALID;
-            if (rc == APRIL_OK) rc = b.run(p, res[k]);
+            if (rc == APRIL_OK) {
+                double cells = 0;   // boundary cells, estimated from the edges' extents
+                if (inner > 1)
+                    for (size_t v = 0; v < p.x.size(); v++) {
+                        const size_t v2 = v + 1 == p.x.size() ? 0 : v + 1;
+                        cells += double(std::llabs(p.x[v2] - p.x[v]) + std::llabs(p.y[v2] - p.y[v])) / double(g.w) + 2;
+                    }
+                rc = (inner > 1 && cells >= par_cells) ? b.run_parallel(p, res[k], inner) : b.run(p, res[k]);
+            }
             if (rc) {
                 res[k].rc = rc;
                 int z = 0;
@@ -344,8 +505,21 @@ extern "C" int april_build_lists(const april_grid_t *grid, const double *xy, con
     if (flags & ~APRIL_STRICT) return fail(APRIL_E_INVALID, "unknown flags");
     std::vector<LatticeGrid> lg(1);
     if (int rc = lattice_grid(grid, &lg[0])) return rc;
-    return build_collection(lg, [](uint64_t) { return 0u; }, *grid, 0, xy, vtx_off, n, flags, out);
+    return build_collection(lg, [](uint64_t) { return 0u; }, *grid, 0, xy, vtx_off, n, flags, out, host_threads());
 }
+
+namespace april {
+int build_lists_threads(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off, uint64_t n,
+                        uint32_t flags, int max_threads, april_lists_t **out) {
+    clear_error();
+    if (!grid || !xy || !vtx_off || !out) return fail(APRIL_E_INVALID, "NULL argument");
+    if (n == 0) return fail(APRIL_E_INVALID, "no polygons");
+    if (flags & ~APRIL_STRICT) return fail(APRIL_E_INVALID, "unknown flags");
+    std::vector<LatticeGrid> lg(1);
+    if (int rc = lattice_grid(grid, &lg[0])) return rc;
+    return build_collection(lg, [](uint64_t) { return 0u; }, *grid, 0, xy, vtx_off, n, flags, out, max_threads);
+}
+}  // namespace april
 
 extern "C" int april_build_lists_partitioned(const april_grid_t *grids, uint32_t n_grids,
                                              const uint32_t *grid_of, const double *xy,
@@ -368,5 +542,5 @@ extern "C" int april_build_lists_partitioned(const april_grid_t *grids, uint32_t
     april_grid_t desc = grids[0];
     desc.flags = APRIL_GRID_PARTITIONED;
     return build_collection(lg, [&](uint64_t k) { return grid_of[k]; }, desc, key, xy, vtx_off, n, flags,
-                            out);
+                            out, host_threads());
 }

@@ -99,6 +99,10 @@ void parallel(int threads, F fn) {
     for (auto &t : th) t.join();
 }
 int host_threads();
+// april_build_lists with at most max_threads host threads (polygons in
+// parallel, or one large polygon split over them)
+int build_lists_threads(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off, uint64_t n,
+                        uint32_t flags, int max_threads, april_lists_t **out);
 
 // Per-device state of the filter: compute-unit count and a one-word flag
 // used by index validation.  Created on first use on each device.

@@ -106,6 +106,7 @@ struct april_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::vector<std::thread> builders;
+    int builders_busy = 0;        // builder threads with a request in hand (under mu)
     std::thread dispatcher;
     int dispatcher_rc = APRIL_OK;
 };
@@ -128,6 +129,7 @@ uint64_t sat_sum(const april_server *sv, uint32_t x0, uint32_t y0, uint32_t x1, 
 void builder_main(april_server *sv) {
     for (;;) {
         Req *q;
+        int threads = 1;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
             sv->cv_build.wait(lk, [&] { return sv->stop || !sv->to_build.empty(); });
@@ -135,11 +137,15 @@ void builder_main(april_server *sv) {
             q = sv->to_build.front();
             sv->to_build.pop_front();
             q->state = RQ_BUILT;   // held by this builder from now on
+            // a large query may use the builders that are idle with nothing
+            // queued; under load every query is built on its own thread
+            threads = sv->to_build.empty() ? int(sv->builders.size()) - sv->builders_busy : 1;
+            sv->builders_busy++;
         }
         const uint64_t nv = q->xy.size() / 2;
         const uint64_t off[2] = {0, nv};
         april_lists_t *L = nullptr;
-        int rc = april_build_lists(&sv->S->grid, q->xy.data(), off, 1, 0, &L);
+        int rc = april::build_lists_threads(&sv->S->grid, q->xy.data(), off, 1, 0, std::max(1, threads), &L);
         if (rc == APRIL_OK) {
             double b[4] = {q->xy[0], q->xy[1], q->xy[0], q->xy[1]};
             for (uint64_t k = 1; k < nv; k++) {
@@ -154,6 +160,7 @@ void builder_main(april_server *sv) {
             if (L->n_a + L->n_f > sv->cap_intervals || q->pair_bound > sv->cap_pairs) rc = APRIL_E_NOMEM;
         }
         std::lock_guard<std::mutex> lk(sv->mu);
+        sv->builders_busy--;
         q->lists = L;
         q->t_built = now_s();
         if (q->cancelled) {   // cancelled while being built

@@ -207,3 +207,38 @@ def test_partitioned_build_and_pairs_match_oracle():
     ro, so = oracle.mbr_join(R, S)
     assert np.array_equal(rg[k], ro) and np.array_equal(sg[k], so)
     assert hR.info().n_objects == len(lay.r_obj)
+
+
+def _one(P, k):
+    a, b = int(P.voff[k]), int(P.voff[k + 1])
+    return PolygonSet(np.ascontiguousarray(P.xy[a:b]), np.array([0, b - a], np.int64))
+
+
+def test_parallel_builder_matches_oracle(monkeypatch):
+    """A polygon built alone takes the multi-threaded path (forced here for
+    every size); its lists equal the oracle's brute-force ones."""
+    monkeypatch.setenv("APRIL_PAR_BUILD_CELLS", "1")
+    R, _, g = synth.configs.tiny()
+    from test_oracle_classify import G6, small_star_polys
+    cases = [(g, R, k) for k in range(0, len(R), 37)]
+    ps = small_star_polys(23, 40, lattice_to_grid_points=True)
+    cases += [(G6, ps, k) for k in range(len(ps))]
+    for grid, P, k in cases:
+        one = _one(P, k)
+        assert _same(april.april_build_lists(grid, one.xy, one.voff, april.STRICT), oracle.build_lists(grid, one)), k
+
+
+def test_parallel_builder_large_polygon_equals_sequential():
+    """A large jagged query polygon: built alone (split over threads) and
+    inside a collection (one thread per polygon) the lists are identical."""
+    S, Q, g = synth.configs.serving(n_s=1000, n_queries=400)
+    mb = Q.mbrs()
+    k = int(np.argmax((mb[:, 2] - mb[:, 0]) * np.diff(Q.voff)))
+    alone = april.april_build_lists(g, _one(Q, k).xy, _one(Q, k).voff, 0)
+    assert alone.info().n_a > 10_000
+    many = Q.subset(np.r_[k, np.arange(64)])     # more polygons than threads
+    both = april.april_build_lists(g, many.xy, many.voff, 0).export()
+    got = alone.export()
+    na, nf = int(both[0][1]), int(both[3][1])
+    assert np.array_equal(got[1], both[1][:na]) and np.array_equal(got[2], both[2][:na])
+    assert np.array_equal(got[4], both[4][:nf]) and np.array_equal(got[5], both[5][:nf])

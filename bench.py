@@ -95,7 +95,15 @@ def cpu_baseline(R, S, g, seconds):
         t_filter += time.perf_counter() - t1
         reps += 1
     value = reps * len(r) / t_filter
+    # one thread, one pass over the same sample (median of three)
+    t1s = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        oracle.filter_pairs_timed(LR, LS, r, s, 1)
+        t1s.append(time.perf_counter() - t1)
+    single = len(r) / float(np.median(t1s))
     return {"value": value, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
+            "single_thread_value": single,
             "sample": (f"all {len(r)} candidate pairs among the {len(inR)} R and {len(inS)} S "
                        f"objects whose MBR centres lie in a {2 * half:.4f}-wide square window; "
                        f"filter repeated {reps}x ({t_filter:.1f} s); list build {build_s:.1f} s "
@@ -344,6 +352,7 @@ def main():
         c = counts.cpu().numpy()
         assert int(c.sum()) == P, f"{name}: counts do not cover every pair"
         d = {"ms_per_step": ms, "kernel_ms": float(launch_ms.mean()),
+             "kernel_ms_median": float(np.median(launch_ms)),
              "kernel_ms_p10": float(np.percentile(launch_ms, 10)),
              "kernel_ms_p90": float(np.percentile(launch_ms, 90)),
              "pairs_per_s": P / (ms / 1e3),
@@ -410,6 +419,21 @@ def main():
         forms["batched"] = form("batched", *timed(fn, args.steps, args.warmup))
         forms["batched"]["tuning"] = cfg
         forms["batched"]["hipgraph"] = not args.no_graph
+        # the same pairs in a seeded random order (no spatial locality between
+        # consecutive pairs); verdicts must follow the permutation
+        perm = torch.from_numpy(np.random.default_rng(0).permutation(P)).to(r.device)
+        rp, sp = r[perm].contiguous(), s[perm].contiguous()
+        vp = torch.empty_like(verdict)
+
+        def batched_random():
+            april.april_filter_pairs(dR, dS, rp, sp, vp, counts, schedule=april.SCHED_BATCHED,
+                                     workspace=ws, stream=stream, **kw)
+
+        rnd_ms, _ = timed(batched_random, max(3, args.steps // 4), 1)
+        assert torch.equal(vp, verdict[perm]), "random-order verdicts differ"
+        forms["batched"]["random_order_kernel_ms"] = float(np.median(rnd_ms))
+        log(f"batched, pairs in random order: {forms['batched']['random_order_kernel_ms']:.3f} ms")
+        del rp, sp, vp, perm
         if "plain" in forms:
             assert torch.equal(verdict, plain_verdict), "batched and plain verdicts differ"
             forms["batched"]["speedup_vs_plain"] = (forms["plain"]["kernel_ms"] /

@@ -330,6 +330,50 @@ int april_serve_stats(april_server_t *server, april_serve_stats_t *stats);
 /* Finish batches in flight, stop the threads, free everything. */
 void april_serve_destroy(april_server_t *server);
 
+/* ---------------------------------------------------------- refinement */
+/* The step after the filter (Sec. 2): the pairs it leaves indecisive are
+ * decided by an exact intersection test of the two polygons. */
+typedef struct april_polys april_polys_t;
+
+/*
+ * Upload n_polys polygons to the current device as exact lattice
+ * coordinates (multiples of 2^-30, int64), with their MBRs.
+ *   xy, vtx_off  as for april_build_lists (>= 3 vertices per polygon, no
+ *                closing duplicate); coordinates below 2^32 in magnitude
+ *   flags        0 (round to the nearest lattice point) or APRIL_STRICT
+ *                (a non-lattice coordinate is an error)
+ * The copy runs on `hip_stream` and is complete on return (the call
+ * synchronizes the stream); free with april_polys_free after the work that
+ * reads the collection is done.
+ * Errors: APRIL_E_INVALID (NULL, n_polys == 0, < 3 vertices, non-lattice
+ * under APRIL_STRICT, coordinate out of range), APRIL_E_NOMEM, APRIL_E_HIP.
+ */
+int april_polys_to_device(const double *xy, const uint64_t *vtx_off, uint64_t n_polys, uint32_t flags,
+                          void *hip_stream, april_polys_t **out);
+
+void april_polys_free(april_polys_t *polys);
+
+/*
+ * Exact refinement: d_out[i] = 1 if polygons R[d_r[i]] and S[d_s[i]] share
+ * at least one point (closed sets: boundary contact counts), 0 if not.
+ * The test: some edge of one meets some edge of the other (exact, in
+ * integers), or else one polygon's first vertex lies inside the other.
+ *   d_verdict  optional (NULL = test every pair): the filter's verdicts for
+ *              the same pairs; APRIL_TN gives 0 and APRIL_TH
+ *              gives 1 without geometry, APRIL_INDECISIVE pairs are tested
+ *   d_counts   optional device uint64[2]: pairs that intersect, pairs
+ *              tested exactly (overwritten)
+ * A pair with an id out of range gets APRIL_BAD_PAIR.  Device pointers,
+ * asynchronous on `hip_stream` (a 256-byte stream-ordered scratch holds the
+ * work counters).
+ * Errors: APRIL_E_INVALID (NULL collections or out array with n_pairs > 0,
+ * n_pairs >= 2^32, collections on another device), APRIL_E_NOMEM (scratch),
+ * APRIL_E_HIP.
+ */
+int april_refine_pairs(const april_polys_t *R, const april_polys_t *S, const uint32_t *d_r,
+                       const uint32_t *d_s, uint64_t n_pairs, const uint8_t *d_verdict, uint8_t *d_out,
+                       unsigned long long *d_counts, void *hip_stream);
+
 /* ---------------------------------------------------------------- misc */
 typedef struct {
     int32_t device;

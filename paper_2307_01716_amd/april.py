@@ -122,6 +122,10 @@ def lib():
     L.april_serve_stats.argtypes = [P, C.POINTER(april_serve_stats_t)]
     L.april_serve_destroy.argtypes = [P]
     L.april_serve_destroy.restype = None
+    L.april_polys_to_device.argtypes = [P, P, u64, u32, P, C.POINTER(P)]
+    L.april_polys_free.argtypes = [P]
+    L.april_polys_free.restype = None
+    L.april_refine_pairs.argtypes = [P, P, P, P, u64, P, P, P, P]
     L.april_last_error.restype = C.c_char_p
     for name in ("april_build_lists", "april_build_lists_partitioned", "april_lists_from_arrays", "april_lists_info",
                  "april_lists_export", "april_lists_to_device", "april_lists_download",
@@ -129,7 +133,8 @@ def lib():
                  "april_alg2_bytes", "april_filter_workspace_size",
                  "april_mbr_join", "april_device_info", "april_serve_create",
                  "april_serve_submit", "april_serve_poll", "april_serve_wait", "april_serve_release",
-                 "april_serve_cancel", "april_serve_stats"):
+                 "april_serve_cancel", "april_serve_stats", "april_polys_to_device",
+                 "april_refine_pairs"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -284,6 +289,49 @@ def april_alg2_bytes(R: Lists, S: Lists, r, s, bytes_out, stream=None) -> int:
     n = int(r.numel())
     return _check(lib().april_alg2_bytes(R.handle, S.handle, _dptr(r), _dptr(s), n,
                                          _dptr(bytes_out), _stream(stream)))
+
+
+class Polys:
+    """Owning handle of a device polygon collection (april_polys_t)."""
+
+    def __init__(self, handle: int):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("polygons were freed")
+        return self._h
+
+    def free(self):
+        if self._h and not _exiting:
+            lib().april_polys_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def april_polys_to_device(xy: np.ndarray, vtx_off: np.ndarray, flags: int = 0, stream=None) -> Polys:
+    """Polygons (CSR form, as for april_build_lists) to the current device."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    vo = np.ascontiguousarray(vtx_off, dtype=np.uint64)
+    h = C.c_void_p()
+    _check(lib().april_polys_to_device(_np(xy), _np(vo), len(vo) - 1, flags, _stream(stream), C.byref(h)))
+    return Polys(h.value)
+
+
+def april_refine_pairs(R: Polys, S: Polys, r, s, out, verdict=None, counts=None, stream=None) -> int:
+    """Exact test of pairs (r[i], s[i]): out[i] = 1 if the polygons share a
+    point, else 0.  r, s: int32/uint32 device tensors [P]; out: uint8 device
+    tensor [P]; verdict: the filter's uint8 verdicts (TN/TH answered without
+    geometry) or None; counts: int64 device tensor [2] or None."""
+    n = int(r.numel())
+    return _check(lib().april_refine_pairs(R.handle, S.handle, _dptr(r), _dptr(s), n, _dptr(verdict),
+                                           _dptr(out), _dptr(counts), _stream(stream)))
 
 
 def april_mbr_join(boxes_r: np.ndarray, boxes_s: np.ndarray):

@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--partitioned", action="store_true",
                     help="partitioned join, raw and compressed lists (own JSON line)")
     ap.add_argument("--part-objects", type=int, default=500_000)
+    ap.add_argument("--refine", action="store_true",
+                    help="exact refinement after the filter, against refining every candidate "
+                         "pair (own JSON line)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="offered arrivals per load level last about this long (at most 10^4 queries)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -272,6 +275,116 @@ def partitioned_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def refine_bench(args):
+    """Refinement on the at-scale workload.  The batched filter's verdicts are
+    computed once (untimed); then three timed forms, each K launches after W
+    warm-up ones, HIP events on the launch stream:
+      refine_ind     april_refine_pairs on the indecisive pairs only;
+      filter_refine  the filter plus a refinement call that takes its
+                     verdicts (only indecisive pairs are tested);
+      refine_all     every candidate pair tested exactly, no filter.
+    The CPU baseline is the oracle's exact test, one pair per call, on
+    indecisive pairs for about --cpu-seconds."""
+    import torch
+
+    import synth
+    from paper_2307_01716_amd import april
+
+    assert torch.cuda.is_available(), "no HIP device"
+    t0 = time.time()
+    R, S, g = synth.configs.scale()
+    r_np, s_np = april.april_mbr_join(R.mbrs(), S.mbrs())
+    P = len(r_np)
+    stream = torch.cuda.current_stream()
+    dR = april.april_lists_to_device(april.april_build_lists(g, R.xy, R.voff, april.STRICT), stream=stream)
+    dS = april.april_lists_to_device(april.april_build_lists(g, S.xy, S.voff, april.STRICT), stream=stream)
+    pR = april.april_polys_to_device(R.xy, R.voff, april.STRICT, stream=stream)
+    pS = april.april_polys_to_device(S.xy, S.voff, april.STRICT, stream=stream)
+    r = torch.from_numpy(r_np.view(np.int32)).cuda()
+    s = torch.from_numpy(s_np.view(np.int32)).cuda()
+    verdict = torch.empty(P, dtype=torch.uint8, device="cuda")
+    fcounts = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
+    april.april_filter_pairs(dR, dS, r, s, verdict, fcounts, schedule=april.SCHED_BATCHED, workspace=ws)
+    torch.cuda.synchronize()
+    v_np = verdict.cpu().numpy()
+    ind = np.nonzero(v_np == april.INDECISIVE)[0]
+    ri, si = r[torch.from_numpy(ind).cuda()], s[torch.from_numpy(ind).cuda()]
+    nv_r, nv_s = np.diff(R.voff), np.diff(S.voff)
+    edge_pairs_ind = int(np.sum(nv_r[r_np[ind]] * nv_s[s_np[ind]]))
+    edge_pairs_all = int(np.sum(nv_r[r_np].astype(np.int64) * nv_s[s_np]))
+    log(f"setup {time.time() - t0:.1f}s: {P} pairs, {len(ind)} indecisive "
+        f"({edge_pairs_ind / 1e6:.1f}M edge pairs; all pairs {edge_pairs_all / 1e9:.2f}G)")
+    out_ind = torch.empty(len(ind), dtype=torch.uint8, device="cuda")
+    out_all = torch.empty(P, dtype=torch.uint8, device="cuda")
+    rc = torch.zeros(2, dtype=torch.int64, device="cuda")
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    forms = {}
+    ms = timed(lambda: april.april_refine_pairs(pR, pS, ri, si, out_ind, counts=rc, stream=stream))
+    hits_ind = int(rc[0].item())
+    forms["refine_ind"] = {"ms": ms, "pairs": len(ind), "pairs_per_s": len(ind) / (ms / 1e3),
+                           "edge_pairs_per_s": edge_pairs_ind / (ms / 1e3), "intersecting": hits_ind}
+    log(f"refine indecisive: {ms:.3f} ms, {len(ind) / ms / 1e3:.2f} M pairs/s, {hits_ind} intersect")
+
+    def pipeline():
+        april.april_filter_pairs(dR, dS, r, s, verdict, fcounts, schedule=april.SCHED_BATCHED, workspace=ws,
+                                 stream=stream)
+        april.april_refine_pairs(pR, pS, r, s, out_all, verdict=verdict, counts=rc, stream=stream)
+    ms = timed(pipeline)
+    c = rc.cpu().numpy()
+    res_filter = out_all.clone()
+    forms["filter_refine"] = {"ms": ms, "pairs_per_s": P / (ms / 1e3), "intersecting": int(c[0]),
+                              "tested": int(c[1])}
+    log(f"filter + refine: {ms:.3f} ms, {P / ms / 1e6:.3f} G pairs/s, {int(c[0])} intersect")
+    ms = timed(lambda: april.april_refine_pairs(pR, pS, r, s, out_all, counts=rc, stream=stream))
+    c = rc.cpu().numpy()
+    assert torch.equal(out_all, res_filter), "refinement with and without the filter disagree"
+    forms["refine_all"] = {"ms": ms, "pairs_per_s": P / (ms / 1e3),
+                           "edge_pairs_per_s": edge_pairs_all / (ms / 1e3), "intersecting": int(c[0]),
+                           "tested": int(c[1])}
+    log(f"refine all: {ms:.3f} ms, {P / ms / 1e6:.3f} G pairs/s; the filter saves "
+        f"{forms['refine_all']['ms'] / forms['filter_refine']['ms']:.2f}x")
+    out = {"metric": "candidate pairs resolved/s (intermediate filter + exact refinement of indecisive pairs)",
+           "value": forms["filter_refine"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms["filter_refine"]["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i64",
+           "data": "synthetic",
+           "config": {"workload": "scale: 200k x 200k star polygons, grid 2^16, all MBR candidate pairs",
+                      "pairs": P, "indecisive": int(len(ind))},
+           "forms": forms,
+           "filter_speedup": forms["refine_all"]["ms"] / forms["filter_refine"]["ms"]}
+    if not args.no_cpu_baseline:
+        import oracle
+        order = np.random.default_rng(3).permutation(ind)
+        done, t_cpu, hits = 0, 0.0, 0
+        while t_cpu < args.cpu_seconds and done < len(order):
+            blk = order[done:done + 2000]
+            t1 = time.perf_counter()
+            for p in blk:
+                hits += oracle.polygons_intersect(R.polygon(int(r_np[p])), S.polygon(int(s_np[p])))
+            t_cpu += time.perf_counter() - t1
+            done += len(blk)
+        out["cpu_baseline"] = {"value": done / t_cpu, "unit": "indecisive pairs/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{done} random indecisive pairs, one exact test per call "
+                                         f"({t_cpu:.1f} s)"}
+        log(f"cpu baseline: {done / t_cpu / 1e3:.1f} K indecisive pairs/s on one thread")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -281,6 +394,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.refine:
+        refine_bench(args)
         return
     if args.partitioned:
         if args.copy_calibration:

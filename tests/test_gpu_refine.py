@@ -12,8 +12,10 @@ Cases:
   * small rectilinear and triangular shapes on a coarse lattice, where
     shared edges, collinear overlaps, touching corners and nesting are
     common;
-  * star polygons with 8 .. 400 vertices (several 64-edge chunks, either
-    side the shorter one);
+  * star polygons with 8 .. 400 vertices (edge chunks of either side
+    gathered several times), and nested ones with no boundary contact;
+  * pairs spanning 2^31 lattice units or more (the 128-bit pass) and the
+    same shapes at small scale;
   * the tiny workload: every MBR candidate pair with no verdict input, and
     with the filter's verdicts as input (TN -> 0 and TH -> 1 without
     geometry);
@@ -160,6 +162,57 @@ def test_star_polygons_many_chunks():
     assert 0 < want.sum() < len(want)
     got, cnt = refine(polys(R), polys(S), r, s)
     assert np.array_equal(got, want)
+
+
+def test_nested_stars_no_contact():
+    """Many-vertex polygons nested inside each other without boundary
+    contact: only the crossing-number test decides (several 64-edge blocks)."""
+    rng = np.random.default_rng(12)
+    n = 24
+    c = 0.5 + 0.01 * rng.standard_normal((n, 2))
+    outer = star_polygons(rng, c, np.full(n, 0.002), rng.integers(100, 600, n))
+    inner = star_polygons(rng, c, np.full(n, 0.0005), rng.integers(100, 600, n))
+    r, s = np.arange(n), np.arange(n)
+    want = want_of(outer, inner, r, s)
+    assert want.all()
+    got, _ = refine(polys(outer), polys(inner), r, s)
+    assert np.array_equal(got, want)
+    got, _ = refine(polys(inner), polys(outer), s, r)
+    assert np.array_equal(got, want)
+
+
+def wide_cases():
+    """Coarse shapes at three scales (the larger two span 2^31 lattice units
+    or more), and one square of side 6 against small shapes across the
+    128-bit boundary: nested, crossing a corner, far away, touching at a
+    vertex, one lattice unit apart."""
+    out = []
+    for scale in (1.0, 2.0 ** 10, 2.0 ** 20):   # shape units of 2^-20, 1 and 2^10
+        R, S = coarse_shapes(np.random.default_rng(31), 40), coarse_shapes(np.random.default_rng(32), 40)
+        r, s = np.meshgrid(np.arange(40), np.arange(40), indexing="ij")
+        out.append((f"x{scale:g}", PolygonSet(R.xy * scale, R.voff), PolygonSet(S.xy * scale, S.voff),
+                    r.ravel(), s.ravel(), None))
+    big = np.array([[-3.0, -3.0], [3.0, -3.0], [3.0, 3.0], [-3.0, 3.0]])
+    box = lambda x, y, w: np.array([[x, y], [x + w, y], [x + w, y + w], [x, y + w]])   # noqa: E731
+    smalls = [box(0.0, 0.0, 0.5), box(-3.5, -3.5, 1.0), box(1000.0, 1000.0, 1.0),
+              np.array([[3.0, 0.0], [4.0, 0.0], [4.0, 1.0]]),
+              np.array([[3.0 + LATTICE, 0.0], [4.0, 0.0], [4.0, 1.0]])]
+    out.append(("big", from_list([big]), from_list(smalls), np.zeros(len(smalls), np.int64),
+                np.arange(len(smalls)), [1, 1, 0, 1, 0]))
+    return out
+
+
+def test_wide_coordinates():
+    """Pairs spanning 2^31 lattice units or more take the 128-bit pass, the
+    same shapes at a small scale the 64-bit one; both match the oracle."""
+    for name, R, S, r, s, expect in wide_cases():
+        want = want_of(R, S, r, s)
+        if expect is not None:
+            assert list(want) == expect
+        say(f"[refine] wide {name}: {int(want.sum())} of {len(r)} intersect")
+        got, cnt = refine(polys(R), polys(S), r, s)
+        assert np.array_equal(got, want)
+        assert list(cnt) == [int(want.sum()), len(r)]
 
 
 @pytest.fixture(scope="module")

@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB three times (reference dispatches for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-random-order", action="store_true",
+                    help="skip the extra timing of the batched kernel on pairs in random order "
+                         "(profiles of the in-order launches)")
     ap.add_argument("--workload", choices=["scale", "skewed"], default="scale",
                     help="scale: 200k x 200k polygons (default); skewed: the same plus 2000 "
                          "complex polygons (20k-100k vertices) per side")
@@ -535,21 +538,22 @@ def main():
         forms["batched"] = form("batched", *timed(fn, args.steps, args.warmup))
         forms["batched"]["tuning"] = cfg
         forms["batched"]["hipgraph"] = not args.no_graph
-        # the same pairs in a seeded random order (no spatial locality between
-        # consecutive pairs); verdicts must follow the permutation
-        perm = torch.from_numpy(np.random.default_rng(0).permutation(P)).to(r.device)
-        rp, sp = r[perm].contiguous(), s[perm].contiguous()
-        vp = torch.empty_like(verdict)
+        if not args.no_random_order:
+            # the same pairs in a seeded random order (no spatial locality
+            # between consecutive pairs); verdicts must follow the permutation
+            perm = torch.from_numpy(np.random.default_rng(0).permutation(P)).to(r.device)
+            rp, sp = r[perm].contiguous(), s[perm].contiguous()
+            vp = torch.empty_like(verdict)
 
-        def batched_random():
-            april.april_filter_pairs(dR, dS, rp, sp, vp, counts, schedule=april.SCHED_BATCHED,
-                                     workspace=ws, stream=stream, **kw)
+            def batched_random():
+                april.april_filter_pairs(dR, dS, rp, sp, vp, counts, schedule=april.SCHED_BATCHED,
+                                         workspace=ws, stream=stream, **kw)
 
-        rnd_ms, _ = timed(batched_random, max(3, args.steps // 4), 1)
-        assert torch.equal(vp, verdict[perm]), "random-order verdicts differ"
-        forms["batched"]["random_order_kernel_ms"] = float(np.median(rnd_ms))
-        log(f"batched, pairs in random order: {forms['batched']['random_order_kernel_ms']:.3f} ms")
-        del rp, sp, vp, perm
+            rnd_ms, _ = timed(batched_random, max(3, args.steps // 4), 1)
+            assert torch.equal(vp, verdict[perm]), "random-order verdicts differ"
+            forms["batched"]["random_order_kernel_ms"] = float(np.median(rnd_ms))
+            log(f"batched, pairs in random order: {forms['batched']['random_order_kernel_ms']:.3f} ms")
+            del rp, sp, vp, perm
         if "plain" in forms:
             assert torch.equal(verdict, plain_verdict), "batched and plain verdicts differ"
             forms["batched"]["speedup_vs_plain"] = (forms["plain"]["kernel_ms"] /

@@ -181,7 +181,9 @@ typedef struct {
     uint32_t flags;        /* APRIL_VALIDATE */
     uint32_t waves;        /* resident wavefronts (0 = library default) */
     uint32_t tile;         /* batched: intervals per list kept in LDS per wavefront:
-                              128, 256 or 512 (0 = 512; compressed lists: 256, 512, 1024) */
+                              128, 256 or 512 (0 = 256 when the two collections' A-lists
+                              average at most 256 intervals, else 512; compressed lists:
+                              256, 512, 1024, 0 = 512) */
     uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2) */
     uint32_t thread_max;   /* batched: pairs whose four lists all have at most this many
                               intervals run one lane per pair (0 = 8) */
@@ -196,8 +198,8 @@ typedef struct {
 } april_filter_opts_t;
 
 /*
- * Device scratch the batched schedule needs for n_pairs pairs: the
- * workgroup queue (4 bytes per pair) and a few counters.
+ * Device scratch the batched schedule needs for n_pairs pairs: its work
+ * counters (8 KiB, whatever n_pairs).
  */
 int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opts, uint64_t *bytes);
 
@@ -364,7 +366,7 @@ void april_polys_free(april_polys_t *polys);
  *   d_counts   optional device uint64[2]: pairs that intersect, pairs
  *              tested exactly (overwritten)
  * A pair with an id out of range gets APRIL_BAD_PAIR.  Device pointers,
- * asynchronous on `hip_stream` (a 256-byte stream-ordered scratch holds the
+ * asynchronous on `hip_stream` (an 8 KiB stream-ordered scratch holds the
  * work counters).
  * Errors: APRIL_E_INVALID (NULL collections or out array with n_pairs > 0,
  * n_pairs >= 2^32, collections on another device), APRIL_E_NOMEM (scratch),

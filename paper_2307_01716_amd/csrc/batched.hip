@@ -63,7 +63,7 @@ constexpr uint32_t kNone = 0xffffffffu;    // no resident object / no upper key 
 
 struct BatchArgs {
     FilterArgs f;
-    unsigned int *xhead;         // [xcds] pairs taken from each XCD's range
+    unsigned int *xhead;         // pairs taken from XCD k's range: xhead[k * kCtrStride]
     uint32_t xcds;
     uint32_t thread_max;
     uint32_t search_min;
@@ -74,10 +74,6 @@ struct BatchArgs {
 
 // ---------------------------------------------------------------- binning
 
-__global__ __launch_bounds__(64) void k_zero_batch(unsigned int *ctr, unsigned long long *counts) {
-    if (threadIdx.x < 64) ctr[threadIdx.x] = 0;
-    if (counts && threadIdx.x < 3) counts[threadIdx.x] = 0;
-}
 
 // ------------------------------------------------------------ join pieces
 
@@ -373,6 +369,12 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
     for (uint32_t k = 0; k < xcds; k++) {
         const uint32_t seg = (my_xcd + k) % xcds;
         const uint64_t lo = b.f.n_pairs * seg / xcds, hi = b.f.n_pairs * (seg + 1) / xcds;
+        if (k > 0) {
+            typedef const __attribute__((address_space(4))) BatchArgs *KArgs;
+            KArgs pb = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+            asm volatile("" : "+s"(pb));
+            if (range_drained(pb->xhead, seg, lo, hi, lane)) continue;
+        }
         for (;;) {
             // The arguments are read afresh for every grab (through a pointer
             // the compiler cannot see through), so they hold no scalar
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
             asm volatile("" : "+s"(pb));
             const __attribute__((address_space(4))) FilterArgs &a = pb->f;
             unsigned int got = 0;
-            if (lane == 0) got = atomicAdd(&pb->xhead[seg], grab);
+            if (lane == 0) got = atomicAdd(&pb->xhead[seg * kCtrStride], grab);
             const uint64_t g0 = lo + uniform(__shfl(got, 0));
             if (g0 >= hi) break;
             const uint64_t g1 = min(hi, g0 + grab);
@@ -463,7 +465,6 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
     }
 }
 
-constexpr uint64_t kCtrBytes = 256;
 
 template <int TILE, int C>
 int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
@@ -500,11 +501,16 @@ int launch_t(const BatchArgs &b, uint32_t chunk, int cus, uint32_t waves, hipStr
 
 uint64_t batched_workspace_bytes(uint64_t) { return kCtrBytes; }
 
-int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? cus / 32 : 1; }
+int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? std::min<int>(cus / 32, kMaxCtrs) : 1; }
+
+__global__ void k_zero_ctrs(unsigned int *ctr, unsigned long long *totals, uint32_t n_totals) {
+    if (threadIdx.x < kMaxCtrs) ctr[threadIdx.x * kCtrStride] = 0;
+    if (totals && threadIdx.x < n_totals) totals[threadIdx.x] = 0;
+}
 
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
                    hipStream_t stream) {
-    const uint32_t tile = o.tile ? o.tile : 512;
+    const uint32_t tile = o.tile ? o.tile : 256;
     const uint32_t chunk = o.chunk ? o.chunk : 2;
     BatchArgs b;
     b.f = a;
@@ -515,7 +521,7 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     b.grab = 64;
     b.tail_grab = 8;
     if (b.thread_max >= tile) return fail(APRIL_E_INVALID, "thread_max must be below tile");
-    k_zero_batch<<<1, 64, 0, stream>>>(b.xhead, a.counts);
+    k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead, a.counts, 3);
     APRIL_HIP_TRY(hipGetLastError());
     switch (tile) {
         case 128: return launch_t<128>(b, chunk, cus, o.waves, stream);

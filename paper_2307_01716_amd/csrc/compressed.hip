@@ -138,9 +138,10 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
     for (uint32_t k = 0; k < a.xcds; k++) {
         const uint32_t seg = (my_xcd + k) % a.xcds;
         const uint64_t lo = a.n_pairs * seg / a.xcds, hi = a.n_pairs * (seg + 1) / a.xcds;
+        if (k > 0 && range_drained(a.xhead, seg, lo, hi, lane)) continue;
         for (;;) {
             unsigned int got = 0;
-            if (lane == 0) got = atomicAdd(&a.xhead[seg], 64u);
+            if (lane == 0) got = atomicAdd(&a.xhead[seg * kCtrStride], 64u);
             const uint64_t g0 = lo + uniform(__shfl(got, 0));
             if (g0 >= hi) break;
             const uint32_t cnt = uint32_t(min<uint64_t>(64, hi - g0));
@@ -182,10 +183,6 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
     }
 }
 
-__global__ void k_zero_vbyte(unsigned int *xhead, unsigned long long *counts) {
-    if (threadIdx.x < 64) xhead[threadIdx.x] = 0;
-    if (counts && threadIdx.x < 3) counts[threadIdx.x] = 0;
-}
 
 // One wave per list: decode it whole into raw start/end arrays.
 __global__ __launch_bounds__(256) void k_decode_lists(const uint8_t *bytes, const uint64_t *boff,
@@ -218,7 +215,7 @@ CList clist(const april_lists_t *L, bool f) {
 
 }  // namespace
 
-uint64_t vbyte_workspace_bytes() { return 256; }
+uint64_t vbyte_workspace_bytes() { return kCtrBytes; }
 
 int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
                         uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
@@ -238,7 +235,7 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
     a.xhead = static_cast<unsigned int *>(workspace);
     a.xcds = uint32_t(xcd_count(cus));
     a.search_min = o.search_min ? o.search_min : 1024;
-    k_zero_vbyte<<<1, 64, 0, stream>>>(a.xhead, counts);
+    k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead, counts, 3);
     APRIL_HIP_TRY(hipGetLastError());
     const uint32_t tile = o.tile ? o.tile : 512;
     const uint64_t blocks = uint64_t(cus) * 8;

@@ -39,6 +39,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Work counters of the persistent kernels (one per XCD range) sit 128 bytes
+// apart: atomics on one cache line are serialized, and with every counter in
+// one line the grabs of the whole chip queue behind each other (measured on
+// the at-scale join: 17% slower).  Counter k is ctr[k * kCtrStride].
+constexpr uint32_t kCtrStride = 32;
+constexpr uint32_t kMaxCtrs = 64;
+constexpr uint64_t kCtrBytes = uint64_t(kMaxCtrs) * kCtrStride * sizeof(unsigned int);
+
+// zero the counters (and up to three uint64 totals)
+__global__ void k_zero_ctrs(unsigned int *ctr, unsigned long long *totals, uint32_t n_totals);
+
+// Has XCD range `seg` ([lo, hi)) been drained?  A plain read, for waves
+// about to help another range: without it, waves that finish together all
+// line up on the drained range's counter.  Whole wave, lane 0 reads.
+__device__ __forceinline__ bool range_drained(const unsigned int *ctr, uint32_t seg, uint64_t lo, uint64_t hi,
+                                              uint32_t lane) {
+    unsigned int taken = 0;
+    if (lane == 0) taken = __hip_atomic_load(&ctr[seg * kCtrStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return lo + uniform(__shfl(taken, 0)) >= hi;
+}
+
 // Alg. 2's IntervalJoin run sequentially by one lane; *rx, *ry receive how
 // many leading elements of X and Y the loop read.
 __device__ inline bool seq_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,

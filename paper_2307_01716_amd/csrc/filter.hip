@@ -288,12 +288,12 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
         if (o.schedule != APRIL_SCHED_BATCHED)
             return fail(APRIL_E_INVALID, "compressed lists need the batched schedule");
         if (o.d_workspace) {
-            if (o.workspace_bytes < 256) return fail(APRIL_E_INVALID, "workspace too small");
+            if (o.workspace_bytes < kCtrBytes) return fail(APRIL_E_INVALID, "workspace too small");
             return launch_filter_vbyte(R, S, d_r, d_s, n_pairs, d_verdict, counts, o, st->cus, o.d_workspace,
                                        stream);
         }
         void *ws = nullptr;
-        hipError_t e = hipMallocAsync(&ws, 256, stream);
+        hipError_t e = hipMallocAsync(&ws, kCtrBytes, stream);
         if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
         const int rc = launch_filter_vbyte(R, S, d_r, d_s, n_pairs, d_verdict, counts, o, st->cus, ws, stream);
         APRIL_HIP_TRY(hipFreeAsync(ws, stream));
@@ -301,6 +301,11 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
     }
     FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, d_verdict, counts);
     if (o.schedule == APRIL_SCHED_BATCHED) {
+        // default tile: 256 intervals when a typical A-list fits it (more
+        // waves per CU), else 512 (fewer pieces for objects that do not
+        // fit).  Measured: 6% faster at 256 on the at-scale join (mean
+        // 177 intervals), 38% slower on the skewed one (mean 990).
+        if (!o.tile) o.tile = R->n_a + S->n_a <= 256 * (R->n + S->n) ? 256 : 512;
         const uint64_t need = batched_workspace_bytes(n_pairs);
         if (o.d_workspace) {
             if (o.workspace_bytes < need) return fail(APRIL_E_INVALID, "workspace too small");

@@ -117,16 +117,17 @@ struct ProbeQuery {
     double x0, y0, x1, y1;
     uint32_t cx0, cy0, cx1, cy1;
 };
-// Candidate pairs (batch query index, S id) of a batch of queries against
-// the uniform MBR grid of S; *count receives the number found (pairs beyond
-// `cap` are not written).
 // Decode the A (f = false) or F lists of compressed device lists into raw
 // device arrays (one wavefront per list).
 int launch_decode_lists(const april_lists_t *L, bool f, uint32_t *out_s, uint32_t *out_e, hipStream_t stream);
-// The filter on compressed lists (compressed.hip); `workspace` holds 256 bytes.
+// The filter on compressed lists (compressed.hip); `workspace` holds the
+// work counters (kCtrBytes).
 int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
                         uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
                         const april_filter_opts_t &o, int cus, void *workspace, hipStream_t stream);
+// Candidate pairs (batch query index, S id) of a batch of queries against
+// the uniform MBR grid of S; *count receives the number found (pairs beyond
+// `cap` are not written).
 int launch_probe(const ProbeQuery *d_q, uint32_t n_q, const uint32_t *cell_off, const uint32_t *cell_ids,
                  const double *boxes, const uint16_t *cells, uint32_t G, uint32_t *pr, uint32_t *ps,
                  uint32_t cap, unsigned int *count, hipStream_t stream);

@@ -30,8 +30,8 @@ import os
 from collections import OrderedDict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-# sources that define the batched kernel's code
-KERNEL_SOURCES = {"k_batched": ["csrc/batched.hip", "csrc/device.hpp"],
+# sources that define each kernel's code and its launch defaults
+KERNEL_SOURCES = {"k_batched": ["csrc/batched.hip", "csrc/device.hpp", "csrc/filter.hip"],
                   "k_filter_plain": ["csrc/filter.hip", "csrc/device.hpp"]}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 

@@ -191,15 +191,17 @@ typedef struct {
                               to the resident list's Hilbert range by a 64-ary search
                               (0 = 512; compressed lists: 1024) */
     uint32_t reserved;     /* must be 0 */
-    void *d_workspace;     /* batched: device scratch of april_filter_workspace_size()
-                              bytes, or NULL to let the library allocate (stream-ordered);
-                              pass one to capture the call in a hipGraph */
+    void *d_workspace;     /* device scratch of april_filter_workspace_size() bytes
+                              (work counters; count sums), or NULL to let the library
+                              allocate it (stream-ordered) when it needs it; pass one to
+                              capture a batched call in a hipGraph */
     uint64_t workspace_bytes;
 } april_filter_opts_t;
 
 /*
- * Device scratch the batched schedule needs for n_pairs pairs: its work
- * counters (8 KiB, whatever n_pairs).
+ * Device scratch a filter call may use: the batched schedule's work
+ * counters and, for any schedule, the slots that sum d_counts (16 KiB,
+ * whatever n_pairs and the schedule).
  */
 int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opts, uint64_t *bytes);
 
@@ -209,15 +211,15 @@ int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opt
  * Schedules (the verdicts are identical):
  *   APRIL_SCHED_PLAIN    one wavefront per pair; the three joins run as
  *                        merge paths over LDS tiles of both lists.
- *   APRIL_SCHED_BATCHED  a binning kernel sorts pairs into three queues by
- *                        list length (lane per pair / wavefront per pair /
- *                        workgroup per pair), then one persistent kernel
- *                        drains them: the shorter side's lists stay in LDS
- *                        (and are reused by consecutive pairs sharing that
- *                        object), the other side's lists are streamed in
- *                        coalesced chunks.  Launches only kernels when a
- *                        workspace is passed, so it can be captured in a
- *                        hipGraph.
+ *   APRIL_SCHED_BATCHED  one persistent kernel takes the pairs in input
+ *                        order (each XCD its own range first): one
+ *                        wavefront per pair keeps one object's lists in LDS
+ *                        (reused while consecutive pairs share the object;
+ *                        cut into key-range pieces when neither fits) and
+ *                        streams the other's in coalesced chunks; pairs
+ *                        whose lists are all very short run one lane per
+ *                        pair.  Launches only kernels when a workspace is
+ *                        passed, so it can be captured in a hipGraph.
  *   R, S        device-resident lists on the same grid (else APRIL_E_GRID)
  *   d_r, d_s    device uint32[n_pairs]: pair p is (R object d_r[p], S object d_s[p])
  *   d_verdict   device uint8[n_pairs]: APRIL_TN / APRIL_TH / APRIL_INDECISIVE,
@@ -366,8 +368,8 @@ void april_polys_free(april_polys_t *polys);
  *   d_counts   optional device uint64[2]: pairs that intersect, pairs
  *              tested exactly (overwritten)
  * A pair with an id out of range gets APRIL_BAD_PAIR.  Device pointers,
- * asynchronous on `hip_stream` (an 8 KiB stream-ordered scratch holds the
- * work counters).
+ * asynchronous on `hip_stream` (a 16 KiB stream-ordered scratch holds the
+ * work counters and the count sums).
  * Errors: APRIL_E_INVALID (NULL collections or out array with n_pairs > 0,
  * n_pairs >= 2^32, collections on another device), APRIL_E_NOMEM (scratch),
  * APRIL_E_HIP.

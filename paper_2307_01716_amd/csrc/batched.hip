@@ -348,7 +348,13 @@ __device__ __forceinline__ PairLists lane_pair(const PairLists &m, uint32_t k) {
 }
 
 template <int TILE, int C>
-__global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
+// Register budget: 8 waves per SIMD where LDS allows it (TILE <= 256).
+// The hardware allocates SGPRs in blocks of 16, and above 80 SGPRs fewer
+// waves fit than the compiler's occupancy estimate says: the kernel at 97
+// SGPRs ran 5 waves per SIMD (2.42 ms at scale), capped to 80 SGPRs and 64
+// VGPRs (16 bytes of spill) it runs 8 (2.11 ms).
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8), amdgpu_num_sgpr(80)))
+void k_batched(BatchArgs b) {
     __shared__ uint32_t lds_words[kWavesPerBlock * 4 * TILE];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = uniform(threadIdx.x >> 6);
@@ -450,18 +456,14 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchArgs b) {
         }
     }
 
-    const FilterArgs &a = b.f;
-    if (a.counts) {
+    if (b.f.counts) {
         for (int off = 32; off > 0; off >>= 1) {
             c_tn += __shfl_down(c_tn, off);
             c_th += __shfl_down(c_th, off);
             c_ind += __shfl_down(c_ind, off);
         }
-        if (lane == 0) {
-            if (c_tn) atomicAdd(&a.counts[0], c_tn);
-            if (c_th) atomicAdd(&a.counts[1], c_th);
-            if (c_ind) atomicAdd(&a.counts[2], c_ind);
-        }
+        const unsigned long long v[3] = {c_tn, c_th, c_ind};
+        if (lane == 0) add_totals(b.xhead, blockIdx.x * kWavesPerBlock + w, v, 3);
     }
 }
 
@@ -475,8 +477,8 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
         per_cu = q < 1 ? 1 : q;
     }
     // default residency (measured on the at-scale join): 4 waves per SIMD
-    // with 512-interval tiles, 6 with 256, as many as fit with 128
-    const int dflt = TILE >= 512 ? 4 : TILE >= 256 ? 6 : per_cu;
+    // with 512-interval tiles, as many as fit (8) with 256 and 128
+    const int dflt = TILE >= 512 ? 4 : per_cu;
     uint64_t blocks = uint64_t(cus) * std::min(per_cu, dflt);
     if (waves) blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
     // a range is near its end once its waves have about two full grabs each left
@@ -484,6 +486,10 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     bb.tail_pairs = 2ull * b.grab * kWavesPerBlock * ((blocks + b.xcds - 1) / b.xcds);
     k_batched<TILE, C><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
     APRIL_HIP_TRY(hipGetLastError());
+    if (b.f.counts) {
+        k_sum_totals<<<1, 64, 0, stream>>>(b.xhead, b.f.counts, 3);
+        APRIL_HIP_TRY(hipGetLastError());
+    }
     return APRIL_OK;
 }
 
@@ -503,9 +509,24 @@ uint64_t batched_workspace_bytes(uint64_t) { return kCtrBytes; }
 
 int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? std::min<int>(cus / 32, kMaxCtrs) : 1; }
 
-__global__ void k_zero_ctrs(unsigned int *ctr, unsigned long long *totals, uint32_t n_totals) {
-    if (threadIdx.x < kMaxCtrs) ctr[threadIdx.x * kCtrStride] = 0;
-    if (totals && threadIdx.x < n_totals) totals[threadIdx.x] = 0;
+__global__ void k_zero_ctrs(unsigned int *ctr) {
+    const uint32_t t = threadIdx.x;
+    if (t < kMaxCtrs) {
+        ctr[t * kCtrStride] = 0;
+        unsigned long long *slot = reinterpret_cast<unsigned long long *>(ctr + kMaxCtrs * kCtrStride) + t * kSlotWords;
+        slot[0] = slot[1] = slot[2] = 0;
+    }
+}
+
+__global__ void k_sum_totals(const unsigned int *ctr, unsigned long long *totals, uint32_t n) {
+    const uint32_t t = threadIdx.x;   // one wave of 64 = kMaxCtrs lanes
+    const unsigned long long *slot =
+        reinterpret_cast<const unsigned long long *>(ctr + kMaxCtrs * kCtrStride) + t * kSlotWords;
+    for (uint32_t k = 0; k < n; k++) {
+        unsigned long long v = slot[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        if (t == 0) totals[k] = v;
+    }
 }
 
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
@@ -521,7 +542,7 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     b.grab = 64;
     b.tail_grab = 8;
     if (b.thread_max >= tile) return fail(APRIL_E_INVALID, "thread_max must be below tile");
-    k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead, a.counts, 3);
+    k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     switch (tile) {
         case 128: return launch_t<128>(b, chunk, cus, o.waves, stream);

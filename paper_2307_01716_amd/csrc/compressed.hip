@@ -177,9 +177,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
         }
     }
     if (a.counts && lane == 0) {
-        if (c_tn) atomicAdd(&a.counts[0], c_tn);
-        if (c_th) atomicAdd(&a.counts[1], c_th);
-        if (c_ind) atomicAdd(&a.counts[2], c_ind);
+        const unsigned long long v[3] = {c_tn, c_th, c_ind};
+        add_totals(a.xhead, blockIdx.x * kWavesPerBlock + w, v, 3);
     }
 }
 
@@ -235,7 +234,7 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
     a.xhead = static_cast<unsigned int *>(workspace);
     a.xcds = uint32_t(xcd_count(cus));
     a.search_min = o.search_min ? o.search_min : 1024;
-    k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead, counts, 3);
+    k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     const uint32_t tile = o.tile ? o.tile : 512;
     const uint64_t blocks = uint64_t(cus) * 8;
@@ -246,6 +245,10 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
         default: return fail(APRIL_E_INVALID, "compressed lists: tile must be 256, 512 or 1024");
     }
     APRIL_HIP_TRY(hipGetLastError());
+    if (counts) {
+        k_sum_totals<<<1, 64, 0, stream>>>(a.xhead, counts, 3);
+        APRIL_HIP_TRY(hipGetLastError());
+    }
     return APRIL_OK;
 }
 

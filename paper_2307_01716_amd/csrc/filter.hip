@@ -81,8 +81,19 @@ __device__ __forceinline__ bool wave_join(const uint32_t *__restrict__ xs, const
 // Workgroups are dealt to the XCDs round-robin, so workgroup b runs on XCD
 // b % xcds; each XCD takes one contiguous range of the pairs, keeping pairs
 // that are close in the input (and share lists) in one L2.
+struct PlainArgs {
+    FilterArgs f;
+    unsigned int *ctr;   // scratch slots that sum the counts
+    uint32_t xcds;
+};
+
+// 80 SGPRs at most: the hardware allocates SGPRs in blocks of 16, and
+// above 80 fewer than 8 waves per SIMD fit (at 81 SGPRs the kernel ran 1.6x
+// longer with a grid of 8 waves per SIMD: part of it ran as a second round).
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_filter_plain(FilterArgs a, uint32_t xcds) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(80))) void k_filter_plain(PlainArgs pa) {
+    const FilterArgs &a = pa.f;
+    const uint32_t xcds = pa.xcds;
     __shared__ uint2 lds[kWavesPerBlock][2][kWave * K];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t w = uniform(threadIdx.x / kWave);
@@ -121,9 +132,14 @@ __global__ __launch_bounds__(kBlock) void k_filter_plain(FilterArgs a, uint32_t 
         c_ind += (v == APRIL_INDECISIVE);
     }
     if (a.counts && lane == 0) {
-        if (c_tn) atomicAdd(&a.counts[0], c_tn);
-        if (c_th) atomicAdd(&a.counts[1], c_th);
-        if (c_ind) atomicAdd(&a.counts[2], c_ind);
+        // the slot pointer is read from the kernel arguments only here, so
+        // it holds no scalar registers during the loop (two more SGPRs cost
+        // this kernel a third of its resident waves)
+        typedef const __attribute__((address_space(4))) PlainArgs *KArgs;
+        KArgs pk = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(pk));
+        const unsigned long long v[3] = {c_tn, c_th, c_ind};
+        add_totals(pk->ctr, blockIdx.x * kWavesPerBlock + w, v, 3);
     }
 }
 
@@ -318,17 +334,43 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
         APRIL_HIP_TRY(hipFreeAsync(ws, stream));
         return rc;
     }
+    // the counts are summed through the scratch slots (the caller's
+    // workspace, else a stream-ordered allocation)
+    void *ws = nullptr;
     if (counts) {
-        k_zero_counts<<<1, 64, 0, stream>>>(counts);
-        APRIL_HIP_TRY(hipGetLastError());
+        if (o.d_workspace) {
+            if (o.workspace_bytes < kCtrBytes) return fail(APRIL_E_INVALID, "workspace too small");
+            ws = o.d_workspace;
+        } else {
+            hipError_t e = hipMallocAsync(&ws, kCtrBytes, stream);
+            if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
+        }
+        k_zero_ctrs<<<1, 64, 0, stream>>>(static_cast<unsigned int *>(ws));
     }
-    uint64_t waves = o.waves ? o.waves : uint64_t(st->cus) * 32;
+    static int per_cu = 0;   // resident workgroups per CU (same on every gfx950 device)
+    if (!per_cu) {
+        int q = 0;
+        APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_filter_plain<4>, kBlock, 0));
+        per_cu = q < 1 ? 1 : q;
+    }
+    // one resident wave per slot: a second round of waves would run the
+    // statically assigned pairs after the first
+    uint64_t waves = o.waves ? o.waves : uint64_t(st->cus) * per_cu * kWavesPerBlock;
     waves = std::min<uint64_t>(waves, n_pairs);
     const uint32_t xcds = uint32_t(xcd_count(st->cus));
     uint64_t blocks = std::max<uint64_t>(1, (waves + kWavesPerBlock - 1) / kWavesPerBlock);
     blocks = (blocks + xcds - 1) / xcds * xcds;   // every XCD gets the same number of workgroups
-    k_filter_plain<4><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a, xcds);
-    APRIL_HIP_TRY(hipGetLastError());
+    PlainArgs pa{a, static_cast<unsigned int *>(ws), xcds};
+    k_filter_plain<4><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(pa);
+    hipError_t e = hipGetLastError();
+    if (counts) {
+        if (e == hipSuccess) {
+            k_sum_totals<<<1, 64, 0, stream>>>(static_cast<unsigned int *>(ws), counts, 3);
+            e = hipGetLastError();
+        }
+        if (!o.d_workspace) APRIL_HIP_TRY(hipFreeAsync(ws, stream));
+    }
+    if (e != hipSuccess) return fail(APRIL_E_HIP, std::string("filter launch: ") + hipGetErrorString(e));
     return APRIL_OK;
 }
 
@@ -336,6 +378,6 @@ extern "C" int april_filter_workspace_size(uint64_t n_pairs, const april_filter_
                                            uint64_t *bytes) {
     clear_error();
     if (!bytes) return fail(APRIL_E_INVALID, "NULL argument");
-    *bytes = (opts && opts->schedule == APRIL_SCHED_BATCHED) || !opts ? batched_workspace_bytes(n_pairs) : 0;
+    *bytes = batched_workspace_bytes(n_pairs);   // plain: the scratch that sums the counts
     return APRIL_OK;
 }

@@ -437,10 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
             c_hit += __shfl_down(c_hit, off);
             c_tested += __shfl_down(c_tested, off);
         }
-        if (lane == 0) {
-            if (c_hit) atomicAdd(&a.counts[0], c_hit);
-            if (c_tested) atomicAdd(&a.counts[1], c_tested);
-        }
+        const unsigned long long v[2] = {c_hit, c_tested};
+        if (lane == 0) add_totals(a.xhead, blockIdx.x * kWavesPerBlock + wave, v, 2);
     }
 }
 
@@ -471,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_wide(RefineArgs a) {
     }
     if (a.counts) {
         for (int off = 32; off > 0; off >>= 1) c_hit += __shfl_down(c_hit, off);
-        if (lane == 0 && c_hit) atomicAdd(&a.counts[0], c_hit);
+        if (lane == 0) add_totals(a.xhead, uint32_t(wave), &c_hit, 1);
     }
 }
 
@@ -598,7 +596,7 @@ extern "C" int april_refine_pairs(const april_polys_t *R, const april_polys_t *S
     hipError_t e = hipMallocAsync(&ws, kCtrBytes, stream);
     if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("refine scratch: ") + hipGetErrorString(e));
     a.xhead = static_cast<unsigned int *>(ws);
-    k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead, d_counts, 2);
+    k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead);
     e = hipGetLastError();
     if (e == hipSuccess && n_pairs) {
         k_refine<<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a);
@@ -607,6 +605,10 @@ extern "C" int april_refine_pairs(const april_polys_t *R, const april_polys_t *S
             k_refine_wide<<<dim3(uint32_t(st->cus)), dim3(kBlock), 0, stream>>>(a);
             e = hipGetLastError();
         }
+    }
+    if (e == hipSuccess && d_counts) {
+        k_sum_totals<<<1, 64, 0, stream>>>(a.xhead, d_counts, 2);
+        e = hipGetLastError();
     }
     APRIL_HIP_TRY(hipFreeAsync(ws, stream));
     if (e != hipSuccess) return fail(APRIL_E_HIP, std::string("refine launch: ") + hipGetErrorString(e));

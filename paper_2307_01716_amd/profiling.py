@@ -77,6 +77,18 @@ def kernel_stats(trace_dir: str):
     return rows
 
 
+def dispatch_times(trace_dir: str, kernel: str):
+    """Durations (ns) of every dispatch of `kernel` in dispatch order, from
+    the --kernel-trace CSV."""
+    path = _one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if short_name(r["Kernel_Name"]).startswith(kernel):
+                rows.append((int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    return [d for _, d in sorted(rows)]
+
+
 def counters(pmc_dir: str):
     """{dispatch id: (kernel, {counter: value summed over dimensions})}."""
     path = _one(os.path.join(pmc_dir, "**", "*counter_collection.csv"))

@@ -109,6 +109,22 @@ int april_build_lists(const april_grid_t *grid, const double *xy, const uint64_t
                       uint64_t n_polys, uint32_t flags, april_lists_t **out);
 
 /*
+ * The same lists built on the current GPU (Sec. 6: edge traversal, Hilbert
+ * ids, one-step intervalization), for the whole collection at once; the
+ * result is identical, bit for bit, to april_lists_to_device(
+ * april_build_lists(...), APRIL_CODEC_RAW).
+ *   grid, xy, vtx_off, n_polys, flags  as for april_build_lists
+ *   hip_stream  the stream the work runs on; the call returns when the lists
+ *               are complete (it synchronizes the stream twice, to size the
+ *               output) and frees its stream-ordered scratch
+ *   out         receives device-resident raw lists; free with april_lists_free
+ * Errors: as april_build_lists (the first failing polygon is reported), and
+ * APRIL_E_INVALID for n_polys >= 2^31, APRIL_E_HIP, APRIL_E_NODEV.
+ */
+int april_build_lists_gpu(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
+                          uint64_t n_polys, uint32_t flags, void *hip_stream, april_lists_t **out);
+
+/*
  * Partitioning (Sec. 5.2): the data space is split into disjoint partitions,
  * each with its own grid (of order <= 16) over its raster area; an object
  * that meets several partitions has one instance per partition.  This builds

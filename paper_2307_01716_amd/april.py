@@ -100,6 +100,7 @@ def lib():
     P, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
     L.april_build_lists.argtypes = [C.POINTER(april_grid_t), P, P, u64, u32, C.POINTER(P)]
     L.april_build_lists_partitioned.argtypes = [P, u32, P, P, P, u64, u32, C.POINTER(P)]
+    L.april_build_lists_gpu.argtypes = [C.POINTER(april_grid_t), P, P, u64, u32, P, C.POINTER(P)]
     L.april_lists_from_arrays.argtypes = [C.POINTER(april_grid_t), u64, P, P, P, P, P, P, i32,
                                           C.POINTER(P)]
     L.april_lists_info.argtypes = [P, C.POINTER(april_lists_info_t)]
@@ -127,7 +128,7 @@ def lib():
     L.april_polys_free.restype = None
     L.april_refine_pairs.argtypes = [P, P, P, P, u64, P, P, P, P]
     L.april_last_error.restype = C.c_char_p
-    for name in ("april_build_lists", "april_build_lists_partitioned", "april_lists_from_arrays", "april_lists_info",
+    for name in ("april_build_lists", "april_build_lists_partitioned", "april_build_lists_gpu", "april_lists_from_arrays", "april_lists_info",
                  "april_lists_export", "april_lists_to_device", "april_lists_download",
                  "april_filter_pairs",
                  "april_alg2_bytes", "april_filter_workspace_size",
@@ -230,6 +231,17 @@ def april_build_lists(grid, xy: np.ndarray, vtx_off: np.ndarray, flags: int = 0)
     g = _grid(grid)
     h = C.c_void_p()
     _check(lib().april_build_lists(C.byref(g), _np(xy), _np(vo), len(vo) - 1, flags, C.byref(h)))
+    return Lists(h.value)
+
+
+def april_build_lists_gpu(grid, xy: np.ndarray, vtx_off: np.ndarray, flags: int = 0, stream=None) -> Lists:
+    """The lists of april_build_lists, built on the current GPU; device lists."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    vo = np.ascontiguousarray(vtx_off, dtype=np.uint64)
+    g = _grid(grid)
+    h = C.c_void_p()
+    _check(lib().april_build_lists_gpu(C.byref(g), _np(xy), _np(vo), len(vo) - 1, flags, _stream(stream),
+                                       C.byref(h)))
     return Lists(h.value)
 
 

@@ -61,9 +61,14 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="served selection queries instead of the batch filter (own JSON line)")
     ap.add_argument("--serve-objects", type=int, default=1_000_000)
+    ap.add_argument("--gpu-build-cells", type=int, default=0,
+                    help="served queries spanning this many grid cells or more are built on the GPU "
+                         "(0: library default 2^20; 4294967295: never)")
     ap.add_argument("--partitioned", action="store_true",
                     help="partitioned join, raw and compressed lists (own JSON line)")
     ap.add_argument("--part-objects", type=int, default=500_000)
+    ap.add_argument("--build", action="store_true",
+                    help="list construction on the GPU against the host builder (own JSON line)")
     ap.add_argument("--refine", action="store_true",
                     help="exact refinement after the filter, against refining every candidate "
                          "pair (own JSON line)")
@@ -117,11 +122,12 @@ def cpu_baseline(R, S, g, seconds):
 
 
 def serve_bench(args):
-    """Served selection queries on one GPU: S device-resident, queries built
-    on host threads, filtered in continuous batches.  Saturation throughput
-    (all queries offered at once), then Poisson arrivals at 0.5, 0.8 and
-    0.95 of it; per level p50/p99 of submit-to-done latency (the library's
-    steady clock), of its host list-build part, and pairs/s."""
+    """Served selection queries on one GPU: S device-resident, query lists
+    built by builder threads (large queries on the GPU), filtered in
+    continuous batches.  Saturation throughput (all queries offered at once),
+    then Poisson arrivals at 0.5, 0.8 and 0.95 of it; per level p50/p99 of
+    submit-to-done latency (the library's steady clock), of its list-build
+    part, and pairs/s."""
     import torch
 
     import synth
@@ -137,7 +143,7 @@ def serve_bench(args):
     torch.cuda.synchronize()
     info = hS.info()
     log(f"S lists: A={info.n_a} F={info.n_f} intervals, built and uploaded in {time.time() - t0:.1f}s")
-    srv = april.Server(dS, S.mbrs())
+    srv = april.Server(dS, S.mbrs(), gpu_build_cells=args.gpu_build_cells)
     warm, n_sat = 1000, 4000
     nq = len(Q)
 
@@ -192,7 +198,8 @@ def serve_bench(args):
            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
            "config": {"workload": f"served: S = {len(S)} star polygons device-resident, grid 2^16; "
                                   "queries 10..10^4 vertices, radius 5e-4..0.05 (log-uniform)",
-                      "slots": st["slots"], "cap_pairs": st["cap_pairs"]},
+                      "slots": st["slots"], "cap_pairs": st["cap_pairs"],
+                      "gpu_build_cells": args.gpu_build_cells or (1 << 20)},
            "served": {"saturation_qps": sat_qps, "saturation_pairs_per_s": sat_pairs / t_sat,
                       "levels": levels}}
     print(json.dumps(out), flush=True)
@@ -275,6 +282,70 @@ def partitioned_bench(args):
                       "instances": [int(len(lay.r_obj)), int(len(lay.s_obj))]},
            "forms": forms,
            "compression": forms["raw"]["device_bytes"] / forms["vbyte"]["device_bytes"]}
+    print(json.dumps(out), flush=True)
+
+
+def build_bench(args):
+    """List construction (Sec. 6) on the GPU against the library's host
+    builder, on the at-scale collection R (200k polygons) and on 200 complex
+    polygons (20k-100k vertices, as in the skewed workload).  A step is
+    one april_build_lists_gpu call (upload, build, lists resident in HBM; the
+    call synchronizes); W untimed calls, then K timed ones, wall clock.  The
+    host builder (all host threads) is timed once per collection.  The CPU
+    baseline is the oracle's builder on a bounded sample of R."""
+    import torch
+
+    import synth
+    from paper_2307_01716_amd import april
+
+    assert torch.cuda.is_available(), "no HIP device"
+    R, S, g = synth.configs.scale()
+    cases = [("scale R: 200k star polygons, grid 2^16", R, g)]
+    big = synth.configs.large_collection(np.random.default_rng(3001), 200, 3)
+    cases.append(("complex: 200 polygons of 20k-100k vertices (the skewed workload's large ones), grid 2^16",
+                  big, synth.grid.grid_covering([big], 16)))
+    forms = {}
+    for name, ps, grid in cases:
+        nv = int(ps.voff[-1])
+        stream = torch.cuda.current_stream()
+        for _ in range(args.warmup):
+            april.april_build_lists_gpu(grid, ps.xy, ps.voff, april.STRICT, stream=stream).free()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            L = april.april_build_lists_gpu(grid, ps.xy, ps.voff, april.STRICT, stream=stream)
+            times.append(time.perf_counter() - t0)
+            inf = L.info()
+            L.free()
+        ms = float(np.median(times)) * 1e3
+        t0 = time.perf_counter()
+        H = april.april_build_lists(grid, ps.xy, ps.voff, april.STRICT)
+        host_ms = (time.perf_counter() - t0) * 1e3
+        assert H.info().n_a == inf.n_a and H.info().n_f == inf.n_f, "GPU and host lists differ in size"
+        del H
+        forms[name] = {"ms": ms, "polygons": len(ps), "vertices": nv, "intervals": int(inf.n_a + inf.n_f),
+                       "polygons_per_s": len(ps) / (ms / 1e3), "vertices_per_s": nv / (ms / 1e3),
+                       "host_builder_ms": host_ms, "speedup_vs_host": host_ms / ms}
+        log(f"{name}: GPU {ms:.1f} ms ({len(ps) / ms / 1e3:.2f} M polygons/s, {nv / ms / 1e3:.1f} M vertices/s); "
+            f"host builder {host_ms:.0f} ms ({host_ms / ms:.1f}x)")
+    first = forms[cases[0][0]]
+    out = {"metric": "polygons built/s (A- and F-lists on the GPU, lists resident in HBM)",
+           "value": first["polygons_per_s"], "unit": "polygons/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": first["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "i64", "data": "synthetic",
+           "config": {"workload": cases[0][0]}, "forms": forms}
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = R.subset(np.arange(0, len(R), 100))
+        t0 = time.perf_counter()
+        oracle.build_lists(g, sample)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "polygons/s",
+                               "cores": int(min(16, len(os.sched_getaffinity(0)))), "kind": "oracle",
+                               "sample": f"every 100th polygon of R ({len(sample)}), the oracle's builder "
+                                         f"({dt:.1f} s)"}
+        log(f"cpu baseline: {len(sample) / dt:.0f} polygons/s")
     print(json.dumps(out), flush=True)
 
 
@@ -413,6 +484,9 @@ def main():
         return
     if args.refine:
         refine_bench(args)
+        return
+    if args.build:
+        build_bench(args)
         return
     if args.partitioned:
         if args.copy_calibration:

@@ -300,6 +300,11 @@ typedef struct {
     uint64_t mem_budget;    /* device bytes for all slots' buffers (0 = 2 GiB) */
     uint32_t max_batch;     /* queries per batch at most (0 = 8192) */
     uint32_t host_threads;  /* query-list builder threads (0 = host cores - 2) */
+    uint32_t gpu_build_cells;   /* a query whose edges span about this many grid cells
+                                   or more has its lists built on the GPU
+                                   (april_build_lists_gpu), the others on the host
+                                   (0 = 2^20, 0xFFFFFFFF = never) */
+    uint32_t reserved;      /* must be 0 */
     april_filter_opts_t filter;   /* batched-filter tuning (schedule/workspace ignored) */
 } april_serve_opts_t;
 

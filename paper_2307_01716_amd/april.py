@@ -62,6 +62,7 @@ class april_device_info_t(C.Structure):
 class april_serve_opts_t(C.Structure):
     _fields_ = [("mbr_grid", C.c_uint32), ("slots", C.c_uint32), ("mem_budget", C.c_uint64),
                 ("max_batch", C.c_uint32), ("host_threads", C.c_uint32),
+                ("gpu_build_cells", C.c_uint32), ("reserved", C.c_uint32),
                 ("filter", april_filter_opts_t)]
 
 
@@ -391,10 +392,10 @@ class Server:
     """april_serve_* on a device-resident collection S (see include/april.h)."""
 
     def __init__(self, S_dev: Lists, s_boxes: np.ndarray, mbr_grid=0, slots=0, mem_budget=0,
-                 max_batch=0, host_threads=0, **tuning):
+                 max_batch=0, host_threads=0, gpu_build_cells=0, **tuning):
         self._S = S_dev
         boxes = np.ascontiguousarray(s_boxes, np.float64)
-        o = april_serve_opts_t(mbr_grid, slots, mem_budget, max_batch, host_threads,
+        o = april_serve_opts_t(mbr_grid, slots, mem_budget, max_batch, host_threads, gpu_build_cells, 0,
                                _opts(SCHED_BATCHED, **tuning))
         h = C.c_void_p()
         _check(lib().april_serve_create(S_dev.handle, _np(boxes), C.byref(o), C.byref(h)))

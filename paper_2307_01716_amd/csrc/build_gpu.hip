@@ -12,13 +12,14 @@
 //  3. one thread per edge writes its entries: key (polygon, Hilbert id,
 //     interior-crossed flag) for cells, key (polygon, row) and crossing x
 //     for centre lines;
-//  4. radix sorts of both key sets; for each polygon the touched cells are
-//     then in Hilbert order, and each row's crossings are contiguous;
+//  4. radix sorts: for each polygon the touched cells are then in Hilbert
+//     order, and each row's crossings contiguous and in x order;
 //  5. one thread per entry keeps the last entry of every (polygon, cell) run
 //     (its flag is the OR of the run's), and a scan compacts them;
 //  6. one thread per touched cell takes the class bits of Alg. 3 (centre of
-//     a border-only cell inside; first cell of the gap after it inside) by
-//     counting the crossings left of the centre in its row;
+//     a border-only cell inside; first cell of the gap after it inside) from
+//     the parity of the crossings left of the centre in its row (two binary
+//     searches);
 //  7. one thread per touched cell decides which A- and F-interval ends it
 //     owns -- a run of A or F cells starts or stops only at a touched cell or
 //     at a gap next to it -- and scans give each end its slot.
@@ -222,13 +223,15 @@ __device__ __forceinline__ uint64_t next_vertex(const EdgeArgs &a, uint64_t v, u
 
 __global__ void k_edges_count(EdgeArgs a, uint64_t *ccount, uint64_t *xcount, uint32_t *ndistinct) {
     const uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= a.nv) return;
-    const uint32_t k = a.poly[v];
+    const uint32_t lane = threadIdx.x & 63;
+    const bool valid = v < a.nv;
+    const uint32_t k = valid ? a.poly[v] : 0xffffffffu;
+    bool distinct = false;
     uint64_t cc = 0, xc = 0;
-    if (!a.bad[k]) {
+    if (valid && !a.bad[k]) {
         const uint64_t v2 = next_vertex(a, v, k);
         const int64_t ax = a.X[v], ay = a.Y[v], bx = a.X[v2], by = a.Y[v2];
-        if (ax != bx || ay != by) atomicAdd(&ndistinct[k], 1u);
+        distinct = ax != bx || ay != by;
         if (a.wide) {
             cc = edge_cells<__int128, false>(ax, ay, bx, by, a.g, 0, nullptr);
             xc = edge_crossings<__int128, false>(ax, ay, bx, by, a.g, 0, nullptr, nullptr);
@@ -237,8 +240,23 @@ __global__ void k_edges_count(EdgeArgs a, uint64_t *ccount, uint64_t *xcount, ui
             xc = edge_crossings<int64_t, false>(ax, ay, bx, by, a.g, 0, nullptr, nullptr);
         }
     }
-    ccount[v] = cc;
-    xcount[v] = xc;
+    if (valid) {
+        ccount[v] = cc;
+        xcount[v] = xc;
+    }
+    // distinct edges per polygon, one atomic per run of equal polygon ids in
+    // the wave (ids are non-decreasing in v; a polygon of 10^5 vertices would
+    // otherwise take 10^5 atomics on one word)
+    const uint32_t kp = __shfl_up(k, 1);
+    const bool head = lane == 0 || kp != k;
+    const uint64_t heads = __ballot(head), flags = __ballot(distinct);
+    if (head && k != 0xffffffffu) {
+        const uint64_t above = lane == 63 ? 0 : heads & ~((2ull << lane) - 1);
+        const uint32_t next = above ? uint32_t(__builtin_ctzll(above)) : 64u;
+        const uint64_t upto = next == 64 ? ~0ull : (1ull << next) - 1;
+        const uint32_t c = uint32_t(__popcll(flags & upto & ~((1ull << lane) - 1)));
+        if (c) atomicAdd(&ndistinct[k], c);
+    }
 }
 
 __global__ void k_check_distinct(const uint32_t *ndistinct, uint64_t n, unsigned long long *err) {
@@ -299,16 +317,23 @@ __global__ void k_first(const uint64_t *cell, const unsigned long long *m_in, ui
 __device__ bool centre_inside(const uint64_t *xkey, const int64_t *xval, uint64_t nx, uint64_t k, uint32_t i,
                               uint32_t j, int64_t w) {
     const uint64_t target = (k << 16) | j;
+    const int64_t Xc = (2 * int64_t(i) + 1) * w;
+    // crossings are sorted by (polygon, row), x ascending within a row: the
+    // count left of the centre is the distance between the row's first entry
+    // and the first entry at or right of the centre
     uint64_t lo = 0, hi = nx;   // first index with key >= target
     while (lo < hi) {
         const uint64_t mid = (lo + hi) / 2;
         if (xkey[mid] < target) lo = mid + 1;
         else hi = mid;
     }
-    const int64_t Xc = (2 * int64_t(i) + 1) * w;
-    uint32_t left = 0;
-    for (uint64_t p = lo; p < nx && xkey[p] == target; p++) left += xval[p] < Xc;
-    return left & 1u;
+    uint64_t a = lo, b = nx;    // first index with (key, x) >= (target, Xc)
+    while (a < b) {
+        const uint64_t mid = (a + b) / 2;
+        if (xkey[mid] == target && xval[mid] < Xc) a = mid + 1;
+        else b = mid;
+    }
+    return (a - lo) & 1u;
 }
 
 struct CellArgs {
@@ -527,6 +552,8 @@ extern "C" int april_build_lists_gpu(const april_grid_t *grid, const double *xy,
     }
     const uint64_t ne = h[1] + h[2], nx = h[3] + h[4];
     if (ne == 0) return fail(APRIL_E_INVALID, "no boundary cells");
+    if (ne >= (1ull << 32) || nx >= (1ull << 32))
+        return fail(APRIL_E_NOMEM, "more than 2^32 boundary-cell entries in one call: split the collection");
 
     // 3-4: emit, then sort both key sets
     uint64_t *d_ck = sc.get<uint64_t>(ne), *d_ck2 = sc.get<uint64_t>(ne);
@@ -540,14 +567,27 @@ extern "C" int april_build_lists_gpu(const april_grid_t *grid, const double *xy,
     need = 0;
     BG_TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, need, d_ck, d_ck2, ne, 0, 33 + kbits, s));
     size_t need2 = 0;
-    BG_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, need2, d_xk, d_xk2, d_xv, d_xv2, nx, 0, 16 + kbits, s));
+    BG_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, need2, d_xk2, d_xk, reinterpret_cast<uint64_t *>(d_xv2),
+                                              reinterpret_cast<uint64_t *>(d_xv), nx, 0, 16 + kbits, s));
     size_t need3 = 0;
     BG_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, need3, d_ck, d_ck2, ne, s));
-    const size_t tmp2 = std::max({need, need2, need3});
+    // doubled crossing x < 2 * cells * w
+    int xbits = 1;
+    while (xbits < 64 && double(uint64_t(1) << xbits) <= 2.0 * double(lg.cells) * double(lg.w)) xbits++;
+    size_t need4 = 0;
+    BG_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, need4, reinterpret_cast<uint64_t *>(d_xv),
+                                              reinterpret_cast<uint64_t *>(d_xv2), d_xk, d_xk2, nx, 0, xbits, s));
+    const size_t tmp2 = std::max({need, need2, need3, need4});
     void *d_tmp2 = sc.get<char>(tmp2);
     if (!d_tmp2) return fail(APRIL_E_NOMEM, "build scratch");
     if (ne) BG_TRY(hipcub::DeviceRadixSort::SortKeys(d_tmp2, need, d_ck, d_ck2, ne, 0, 33 + kbits, s));
-    if (nx) BG_TRY(hipcub::DeviceRadixSort::SortPairs(d_tmp2, need2, d_xk, d_xk2, d_xv, d_xv2, nx, 0, 16 + kbits, s));
+    // crossings: by x first, then (stable) by (polygon, row), so that x is
+    // ascending within a row; x >= 0 (relative coordinates are positive)
+    if (nx) {
+        uint64_t *xv = reinterpret_cast<uint64_t *>(d_xv), *xv2 = reinterpret_cast<uint64_t *>(d_xv2);
+        BG_TRY(hipcub::DeviceRadixSort::SortPairs(d_tmp2, need4, xv, xv2, d_xk, d_xk2, nx, 0, xbits, s));
+        BG_TRY(hipcub::DeviceRadixSort::SortPairs(d_tmp2, need2, d_xk2, d_xk, xv2, xv, nx, 0, 16 + kbits, s));
+    }
 
     // 5: one entry per (polygon, cell); d_ck is free again and holds the flags
     uint64_t *keep = d_ck, *pos = sc.get<uint64_t>(ne), *cell = sc.get<uint64_t>(ne);
@@ -561,7 +601,7 @@ extern "C" int april_build_lists_gpu(const april_grid_t *grid, const double *xy,
     k_compact<<<blocks_for(ne), kThreads, 0, s>>>(d_ck2, keep, pos, ne, cell, d_m);
     k_first<<<blocks_for(ne), kThreads, 0, s>>>(cell, d_m, n, first);
     // 6-7: classes, interval ends and their slots
-    CellArgs ca{cell, first, d_m, d_xk2, d_xv2, nx, g};
+    CellArgs ca{cell, first, d_m, d_xk, d_xv, nx, g};
     k_classify<<<blocks_for(ne), kThreads, 0, s>>>(ca, ne, cls);
     k_count_ends<<<blocks_for(ne), kThreads, 0, s>>>(ca, cls, ne, na, nf);
     BG_TRY(hipGetLastError());

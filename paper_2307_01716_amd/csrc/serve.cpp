@@ -87,6 +87,8 @@ struct april_server {
     const april_lists_t *S = nullptr;
     int device = 0;
     april_filter_opts_t fopts{};
+    double cell_lattice = 1;       // grid cell side of S, lattice units
+    double gpu_build_cells = 0;    // queries spanning this many cells or more build on the GPU
     // MBR grid index of S
     uint32_t G = 0;
     double lo[2] = {0, 0}, cs = 1;
@@ -126,7 +128,26 @@ uint64_t sat_sum(const april_server *sv, uint32_t x0, uint32_t y0, uint32_t x1, 
     return at(x1 + 1, y1 + 1) - at(x0, y1 + 1) - at(x1 + 1, y0) + at(x0, y0);
 }
 
+// Boundary cells of a query, estimated from its edges' extents (in cells).
+double est_cells(const april_server *sv, const std::vector<double> &xy) {
+    const size_t nv = xy.size() / 2;
+    double cells = 0;
+    for (size_t v = 0; v < nv; v++) {
+        const size_t v2 = v + 1 == nv ? 0 : v + 1;
+        cells += (std::fabs(xy[2 * v2] - xy[2 * v]) + std::fabs(xy[2 * v2 + 1] - xy[2 * v + 1])) * 1073741824.0 /
+                     sv->cell_lattice + 2;
+    }
+    return cells;
+}
+
 void builder_main(april_server *sv) {
+    hipStream_t gpu_stream = nullptr;   // this thread's stream for GPU builds
+    struct StreamGuard {
+        hipStream_t &s;
+        ~StreamGuard() {
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } guard{gpu_stream};
     for (;;) {
         Req *q;
         int threads = 1;
@@ -145,7 +166,25 @@ void builder_main(april_server *sv) {
         const uint64_t nv = q->xy.size() / 2;
         const uint64_t off[2] = {0, nv};
         april_lists_t *L = nullptr;
-        int rc = april::build_lists_threads(&sv->S->grid, q->xy.data(), off, 1, 0, std::max(1, threads), &L);
+        int rc;
+        if (est_cells(sv, q->xy) >= sv->gpu_build_cells) {
+            // a large query: built on the device (host lists identical to the
+            // host builder's), then read back for the batch's staging
+            rc = APRIL_OK;
+            if (!gpu_stream) {
+                if (hipSetDevice(sv->device) != hipSuccess ||
+                    hipStreamCreateWithFlags(&gpu_stream, hipStreamNonBlocking) != hipSuccess) {
+                    gpu_stream = nullptr;
+                    rc = fail(APRIL_E_HIP, "builder stream");
+                }
+            }
+            april_lists_t *Ld = nullptr;
+            if (rc == APRIL_OK) rc = april_build_lists_gpu(&sv->S->grid, q->xy.data(), off, 1, 0, gpu_stream, &Ld);
+            if (rc == APRIL_OK) rc = april_lists_download(Ld, gpu_stream, &L);
+            if (Ld) april_lists_free(Ld);
+        } else {
+            rc = april::build_lists_threads(&sv->S->grid, q->xy.data(), off, 1, 0, std::max(1, threads), &L);
+        }
         if (rc == APRIL_OK) {
             double b[4] = {q->xy[0], q->xy[1], q->xy[0], q->xy[1]};
             for (uint64_t k = 1; k < nv; k++) {
@@ -462,6 +501,20 @@ int april_serve_create(const april_lists_t *S, const double *boxes, const april_
     sv->device = S->device;
     sv->fopts = o.filter;
     sv->G = G;
+    {
+        april::LatticeGrid lg;
+        if (int rc = april::lattice_grid(&S->grid, &lg)) {
+            delete sv;
+            return rc;
+        }
+        sv->cell_lattice = double(lg.w);
+        sv->gpu_build_cells = o.gpu_build_cells == 0xFFFFFFFFu ? 1e300
+                              : o.gpu_build_cells ? double(o.gpu_build_cells) : 1048576.0;
+    }
+    if (o.reserved) {
+        delete sv;
+        return fail(APRIL_E_INVALID, "reserved option must be 0");
+    }
     // per-slot capacities: 70% of a slot's share for pairs (13 bytes each:
     // two ids, a verdict, a queue entry), 30% for query intervals (8 bytes)
     const uint64_t per_slot = budget / nslots;

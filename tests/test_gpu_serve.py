@@ -4,7 +4,9 @@
   S objects whose closed MBR meets the query's, with Alg. 2's verdicts;
 * a request's result is the same alone and in a mix of concurrent requests;
 * a request larger than a slot fails with APRIL_E_NOMEM without disturbing
-  the others; cancelled requests disappear; unknown tickets are errors.
+  the others; cancelled requests disappear; unknown tickets are errors;
+* query lists built on the GPU (every query, or the large ones by default)
+  give the same results as lists built on the host.
 """
 
 import sys
@@ -81,6 +83,27 @@ def test_alone_equals_mix_and_oracle(served):
         say(f"[serve] {total} pairs; p50 {np.median(lat) * 1e3:.1f} ms")
     finally:
         srv.close()
+
+
+def test_gpu_built_queries_equal_host_built(served):
+    S, Q, g, hS, dS = served
+    results = {}
+    for name, cells in (("host", 0xFFFFFFFF), ("gpu", 1)):
+        srv = april.Server(dS, S.mbrs(), slots=3, mem_budget=256 << 20, gpu_build_cells=cells)
+        try:
+            say(f"[serve] all queries built on the {name}")
+            tickets = [srv.submit(Q.polygon(k)) for k in range(len(Q))]
+            results[name] = [srv.wait(t, 300) for t in tickets]
+            for r in results[name]:
+                assert r.status == april.OK
+            results[name] = [(r.s_ids.copy(), r.verdict.copy()) for r in results[name]]
+            for t in tickets:
+                srv.release(t)
+        finally:
+            srv.close()
+    for k, (a, b) in enumerate(zip(results["host"], results["gpu"])):
+        assert np.array_equal(a[0], b[0]), k
+        assert np.array_equal(a[1], b[1]), k
 
 
 def test_admission_limits_and_cancel(served):

@@ -14,6 +14,11 @@ Functions (each follows the paper passage named in oracle.c):
     mbr_join(R, S)                    candidate pairs (closed MBRs meet)
     polygons_intersect(a, b)          exact closed-polygon intersection
     twice_area(poly)                  exact shoelace area x2 (lattice units^2)
+    filter_within(LR, LS, r, s)       within-join filter (Sec. 4.3.2)
+    build_cells(grid, lines)          linestring cell lists (Sec. 4.3.3)
+    filter_linestrings(LP, CL, p, l)  polygon-linestring filter (Sec. 4.3.3)
+    filter_mixed(LR, NR, LS, NS, r, s) Alg. 2 across grid orders (Sec. 5.3)
+    point_in_closed_polygon, linestring_meets_polygon   exact geometry
 
 Parity is pinned for every function by tests/test_oracle_*.py against
 closed forms, brute force and invariants; see those files.
@@ -73,6 +78,16 @@ def _load():
     L.orc_pairs_free.argtypes = [P]
     L.orc_polygons_intersect.argtypes = [P, i64, P, i64]
     L.orc_twice_area.argtypes = [P, i64, C.POINTER(i64), C.POINTER(u64)]
+    L.orc_filter_within.argtypes = [P] * 11 + [i64, P]
+    L.orc_build_cells.argtypes = [d, d, d, i32, P, P, i64, C.POINTER(P)]
+    L.orc_cells_size.restype = i64
+    L.orc_cells_size.argtypes = [P]
+    L.orc_cells_export.argtypes = [P, P, P]
+    L.orc_cells_free.argtypes = [P]
+    L.orc_filter_linestrings.argtypes = [P] * 10 + [i64, P]
+    L.orc_filter_mixed.argtypes = [P] * 6 + [i32] + [P] * 6 + [i32, P, P, i64, P]
+    L.orc_point_in_closed_polygon.argtypes = [P, i64, d, d]
+    L.orc_linestring_meets_polygon.argtypes = [P, i64, P, i64]
     _lib = L
     return L
 
@@ -277,3 +292,81 @@ def partitioned_filter(layout, R, S, nthreads: int = 0):
     v = np.concatenate([o[2] for o in out])
     order = np.lexsort((s, r))
     return r[order], s[order], v[order]
+
+
+# ------------------------------------------------ query variants (Sec. 4.3, 5.3)
+
+def _pairs(r, s):
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    s = np.ascontiguousarray(s, dtype=np.uint32)
+    assert len(r) == len(s)
+    return r, s
+
+
+def filter_within(LR: Lists, LS: Lists, r, s):
+    """Within join filter (Sec. 4.3.2): is r within s?  0 TN, 1 TH, 2 IND."""
+    r, s = _pairs(r, s)
+    v = np.empty(len(r), np.uint8)
+    _check(_load().orc_filter_within(_p(LR.offA), _p(LR.sA), _p(LR.eA), _p(LS.offA), _p(LS.sA), _p(LS.eA),
+                                     _p(LS.offF), _p(LS.sF), _p(LS.eF), _p(r), _p(s), len(r), _p(v)))
+    return v
+
+
+@dataclass
+class Cells:
+    """Linestring approximations: per linestring the sorted cell ids."""
+    off: np.ndarray
+    ids: np.ndarray
+
+    def __len__(self):
+        return len(self.off) - 1
+
+    def cells(self, k):
+        return self.ids[int(self.off[k]):int(self.off[k + 1])]
+
+
+def build_cells(grid, lines) -> Cells:
+    """Cell lists of linestrings (Sec. 4.3.3); `lines` has .xy and .voff
+    like a polygon set (vertices in order, not closed)."""
+    L = _load()
+    xy = np.ascontiguousarray(lines.xy, dtype=np.float64)
+    voff = np.ascontiguousarray(lines.voff, dtype=np.int64)
+    h = C.c_void_p()
+    _check(L.orc_build_cells(*_grid_args(grid), _p(xy), _p(voff), len(voff) - 1, C.byref(h)))
+    try:
+        n = L.orc_cells_size(h)
+        out = Cells(np.empty(len(voff), np.uint64), np.empty(n, np.uint32))
+        L.orc_cells_export(h, _p(out.off), _p(out.ids))
+    finally:
+        L.orc_cells_free(h)
+    return out
+
+
+def filter_linestrings(LP: Lists, CL: Cells, p, l):
+    """Polygon-linestring filter (Sec. 4.3.3).  0 TN, 1 TH, 2 IND."""
+    p, l = _pairs(p, l)
+    v = np.empty(len(p), np.uint8)
+    _check(_load().orc_filter_linestrings(_p(LP.offA), _p(LP.sA), _p(LP.eA), _p(LP.offF), _p(LP.sF), _p(LP.eF),
+                                          _p(CL.off), _p(CL.ids), _p(p), _p(l), len(p), _p(v)))
+    return v
+
+
+def filter_mixed(LR: Lists, NR: int, LS: Lists, NS: int, r, s):
+    """Alg. 2 across grid orders NR and NS on one data space (Sec. 5.3)."""
+    r, s = _pairs(r, s)
+    v = np.empty(len(r), np.uint8)
+    _check(_load().orc_filter_mixed(_p(LR.offA), _p(LR.sA), _p(LR.eA), _p(LR.offF), _p(LR.sF), _p(LR.eF), NR,
+                                    _p(LS.offA), _p(LS.sA), _p(LS.eA), _p(LS.offF), _p(LS.sF), _p(LS.eF), NS,
+                                    _p(r), _p(s), len(r), _p(v)))
+    return v
+
+
+def point_in_closed_polygon(poly: np.ndarray, x: float, y: float) -> bool:
+    poly = np.ascontiguousarray(poly, dtype=np.float64)
+    return bool(_check(_load().orc_point_in_closed_polygon(_p(poly), len(poly), float(x), float(y))))
+
+
+def linestring_meets_polygon(line: np.ndarray, poly: np.ndarray) -> bool:
+    line = np.ascontiguousarray(line, dtype=np.float64)
+    poly = np.ascontiguousarray(poly, dtype=np.float64)
+    return bool(_check(_load().orc_linestring_meets_polygon(_p(line), len(line), _p(poly), len(poly))))

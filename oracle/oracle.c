@@ -784,3 +784,257 @@ void orc_twice_area(const double *xy, int64_t nv, int64_t *hi, uint64_t *lo)
     *hi = (int64_t)(acc >> 64);
     *lo = (uint64_t)acc;
 }
+
+/* ------------------------------------------ public: query variants (Sec. 4.3, 5.3) */
+
+/*
+ * Within join (Sec. 4.3.2): is r within s?  Two of Alg. 2's steps:
+ *   AA-join: no overlap -> true negative (r and s are disjoint);
+ *   every interval of A(r) inside one interval of F(s) -> true hit (every
+ *   cell r meets is Full in s, so r lies inside s);
+ *   otherwise indecisive.
+ * F-lists hold maximal runs, so an A(r) interval inside F(s) as a cell set
+ * lies inside a single F(s) interval.  The test walks both lists once.
+ */
+static int a_inside_f(const uint32_t *as, const uint32_t *ae, uint64_t n,
+                      const uint32_t *fs, const uint32_t *fe, uint64_t m)
+{
+    uint64_t j = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        while (j < m && fe[j] <= as[i]) j++;       /* F intervals ending before this A starts */
+        if (j == m || !(fs[j] <= as[i] && ae[i] <= fe[j])) return 0;
+    }
+    return 1;
+}
+
+int orc_filter_within(const uint64_t *oAr, const uint32_t *sAr, const uint32_t *eAr,
+                      const uint64_t *oAs, const uint32_t *sAs, const uint32_t *eAs,
+                      const uint64_t *oFs, const uint32_t *sFs, const uint32_t *eFs,
+                      const uint32_t *r, const uint32_t *s, int64_t P, uint8_t *verdict)
+{
+    for (int64_t p = 0; p < P; p++) {
+        const uint64_t a0 = oAr[r[p]], a1 = oAr[r[p] + 1];
+        const uint64_t b0 = oAs[s[p]], b1 = oAs[s[p] + 1];
+        const uint64_t f0 = oFs[s[p]], f1 = oFs[s[p] + 1];
+        if (!orc_interval_join(sAr + a0, eAr + a0, a1 - a0, sAs + b0, eAs + b0, b1 - b0, NULL, NULL))
+            verdict[p] = V_TN;
+        else if (a_inside_f(sAr + a0, eAr + a0, a1 - a0, sFs + f0, eFs + f0, f1 - f0))
+            verdict[p] = V_TH;
+        else
+            verdict[p] = V_IND;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Linestring approximation (Sec. 4.3.3): a linestring covers no cell, so it
+ * is kept as the sorted list of the ids of the cells whose closed square one
+ * of its segments meets (all of them Partial).  Brute force: every cell of
+ * each segment's bounding window is tested against the segment.
+ */
+typedef struct { uint64_t *off; uint32_t *ids; int64_t n; } orc_cells;
+
+int orc_build_cells(double x0, double y0, double side, int order, const double *xy,
+                    const int64_t *voff, int64_t n, orc_cells **out)
+{
+    grid_t g;
+    int rc = make_grid(x0, y0, side, order, &g);
+    if (rc) return rc;
+    orc_cells *C = (orc_cells *)calloc(1, sizeof(orc_cells));
+    if (!C) return ORC_E_NOMEM;
+    C->n = n;
+    C->off = (uint64_t *)malloc(sizeof(uint64_t) * (n + 1));
+    vec_t all = {0, 0, 0};
+    if (!C->off) { free(C); return ORC_E_NOMEM; }
+    C->off[0] = 0;
+    for (int64_t k = 0; k < n && !rc; k++) {
+        const int64_t v0 = voff[k], nv = voff[k + 1] - voff[k];
+        if (nv < 2) { rc = ORC_E_INVALID; break; }
+        int64_t *X = (int64_t *)malloc(sizeof(int64_t) * nv), *Y = (int64_t *)malloc(sizeof(int64_t) * nv);
+        if (!X || !Y) { free(X); free(Y); rc = ORC_E_NOMEM; break; }
+        for (int64_t v = 0; v < nv && !rc; v++) {
+            rc = lattice(xy[2 * (v0 + v)], g.x0, &X[v]);
+            if (!rc) rc = lattice(xy[2 * (v0 + v) + 1], g.y0, &Y[v]);
+            /* the same guard ring as for polygons */
+            if (!rc && (X[v] <= g.W || Y[v] <= g.W || X[v] >= (g.n - 1) * g.W || Y[v] >= (g.n - 1) * g.W))
+                rc = ORC_E_GRID;
+        }
+        vec_t ids = {0, 0, 0};
+        for (int64_t v = 0; v + 1 < nv && !rc; v++) {
+            const int64_t mnx = X[v] < X[v + 1] ? X[v] : X[v + 1], mxx = X[v] < X[v + 1] ? X[v + 1] : X[v];
+            const int64_t mny = Y[v] < Y[v + 1] ? Y[v] : Y[v + 1], mxy = Y[v] < Y[v + 1] ? Y[v + 1] : Y[v];
+            /* cells (i, j) with iW <= mxx and (i+1)W >= mnx, same for j */
+            for (int64_t j = ceildiv(mny, g.W) - 1; j <= floordiv(mxy, g.W) && !rc; j++)
+                for (int64_t i = ceildiv(mnx, g.W) - 1; i <= floordiv(mxx, g.W) && !rc; i++)
+                    if (seg_meets_box(X[v], Y[v], X[v + 1], Y[v + 1], i * g.W, j * g.W, (i + 1) * g.W,
+                                      (j + 1) * g.W, 0))
+                        rc = vec_push(&ids, orc_hilbert(g.order, (uint64_t)i, (uint64_t)j));
+        }
+        free(X); free(Y);
+        if (!rc) {
+            qsort(ids.v, ids.n, sizeof(uint64_t), cmp_u64);
+            for (int64_t t = 0; t < ids.n && !rc; t++)
+                if (t == 0 || ids.v[t] != ids.v[t - 1]) rc = vec_push(&all, ids.v[t]);
+        }
+        free(ids.v);
+        C->off[k + 1] = (uint64_t)all.n;
+    }
+    if (!rc) {
+        C->ids = (uint32_t *)malloc(sizeof(uint32_t) * (all.n ? all.n : 1));
+        if (!C->ids) rc = ORC_E_NOMEM;
+        for (int64_t t = 0; t < all.n && !rc; t++) C->ids[t] = (uint32_t)all.v[t];
+    }
+    free(all.v);
+    if (rc) { free(C->off); free(C->ids); free(C); return rc; }
+    *out = C;
+    return ORC_OK;
+}
+
+int64_t orc_cells_size(const orc_cells *C) { return (int64_t)C->off[C->n]; }
+
+void orc_cells_export(const orc_cells *C, uint64_t *off, uint32_t *ids)
+{
+    memcpy(off, C->off, sizeof(uint64_t) * (C->n + 1));
+    memcpy(ids, C->ids, sizeof(uint32_t) * C->off[C->n]);
+}
+
+void orc_cells_free(orc_cells *C)
+{
+    if (!C) return;
+    free(C->off); free(C->ids); free(C);
+}
+
+/*
+ * Polygon-linestring join (Sec. 4.3.3): Alg. 2's IntervalJoin with the
+ * linestring's cell ids as intervals [c, c+1):
+ *   A(p) against the cells: no overlap -> true negative;
+ *   F(p) against the cells: an overlap -> true hit;
+ *   otherwise indecisive.
+ */
+int orc_filter_linestrings(const uint64_t *oAp, const uint32_t *sAp, const uint32_t *eAp,
+                           const uint64_t *oFp, const uint32_t *sFp, const uint32_t *eFp,
+                           const uint64_t *offL, const uint32_t *ids,
+                           const uint32_t *pp, const uint32_t *ll, int64_t P, uint8_t *verdict)
+{
+    for (int64_t q = 0; q < P; q++) {
+        const uint64_t c0 = offL[ll[q]], c1 = offL[ll[q] + 1], m = c1 - c0;
+        uint32_t *cs = (uint32_t *)malloc(sizeof(uint32_t) * (m ? m : 1));
+        uint32_t *ce = (uint32_t *)malloc(sizeof(uint32_t) * (m ? m : 1));
+        if (!cs || !ce) { free(cs); free(ce); return ORC_E_NOMEM; }
+        for (uint64_t t = 0; t < m; t++) { cs[t] = ids[c0 + t]; ce[t] = ids[c0 + t] + 1; }
+        const uint64_t a0 = oAp[pp[q]], a1 = oAp[pp[q] + 1], f0 = oFp[pp[q]], f1 = oFp[pp[q] + 1];
+        if (!orc_interval_join(sAp + a0, eAp + a0, a1 - a0, cs, ce, m, NULL, NULL)) verdict[q] = V_TN;
+        else if (orc_interval_join(sFp + f0, eFp + f0, f1 - f0, cs, ce, m, NULL, NULL)) verdict[q] = V_TH;
+        else verdict[q] = V_IND;
+        free(cs); free(ce);
+    }
+    return ORC_OK;
+}
+
+/*
+ * Different granularity (Sec. 5.3): R's lists at order NR, S's at order NS
+ * on the same data space.  The finer side's A-intervals are mapped to the
+ * coarser grid by the paper's equation, a' = [a_start >> n, (a_end - 1) >> n]
+ * (inclusive end; n = 2 |NR - NS| bits), and the mapped intervals, which may
+ * now touch or overlap, are merged into maximal half-open runs.  Then:
+ *   mapped A against the coarse A-list: no overlap -> true negative;
+ *   mapped A against the coarse F-list: an overlap -> true hit (the only
+ *   one of AF / FA kept: a Full interval at the finer order says nothing
+ *   about the coarser one);
+ *   otherwise indecisive.
+ * With NR == NS nothing is mapped and Alg. 2 runs unchanged.
+ */
+static uint64_t coarsen(const uint32_t *as, const uint32_t *ae, uint64_t n, int bits, uint32_t *os, uint32_t *oe)
+{
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        const uint32_t s = as[i] >> bits, e = ((ae[i] - 1) >> bits) + 1;   /* half-open form of a' */
+        if (k && s <= oe[k - 1]) { if (e > oe[k - 1]) oe[k - 1] = e; }   /* touches or overlaps: merge */
+        else { os[k] = s; oe[k] = e; k++; }
+    }
+    return k;
+}
+
+int orc_filter_mixed(const uint64_t *oAr, const uint32_t *sAr, const uint32_t *eAr,
+                     const uint64_t *oFr, const uint32_t *sFr, const uint32_t *eFr, int NR,
+                     const uint64_t *oAs, const uint32_t *sAs, const uint32_t *eAs,
+                     const uint64_t *oFs, const uint32_t *sFs, const uint32_t *eFs, int NS,
+                     const uint32_t *r, const uint32_t *s, int64_t P, uint8_t *verdict)
+{
+    if (NR == NS) {
+        filter_job_t J;
+        J.oAr = oAr; J.oFr = oFr; J.oAs = oAs; J.oFs = oFs;
+        J.sAr = sAr; J.eAr = eAr; J.sFr = sFr; J.eFr = eFr;
+        J.sAs = sAs; J.eAs = eAs; J.sFs = sFs; J.eFs = eFs;
+        for (int64_t p = 0; p < P; p++) verdict[p] = april_pair(&J, r[p], s[p], NULL);
+        return ORC_OK;
+    }
+    const int r_fine = NR > NS, bits = 2 * (r_fine ? NR - NS : NS - NR);
+    for (int64_t p = 0; p < P; p++) {
+        /* fine side: its A-list; coarse side: A- and F-lists */
+        const uint64_t *oAf = r_fine ? oAr : oAs, *oAc = r_fine ? oAs : oAr, *oFc = r_fine ? oFs : oFr;
+        const uint32_t *sAf = r_fine ? sAr : sAs, *eAf = r_fine ? eAr : eAs;
+        const uint32_t *sAc = r_fine ? sAs : sAr, *eAc = r_fine ? eAs : eAr;
+        const uint32_t *sFc = r_fine ? sFs : sFr, *eFc = r_fine ? eFs : eFr;
+        const uint32_t of = r_fine ? r[p] : s[p], oc = r_fine ? s[p] : r[p];
+        const uint64_t a0 = oAf[of], n = oAf[of + 1] - a0;
+        uint32_t *ms = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+        uint32_t *me = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+        if (!ms || !me) { free(ms); free(me); return ORC_E_NOMEM; }
+        const uint64_t m = coarsen(sAf + a0, eAf + a0, n, bits, ms, me);
+        const uint64_t c0 = oAc[oc], c1 = oAc[oc + 1], f0 = oFc[oc], f1 = oFc[oc + 1];
+        if (!orc_interval_join(ms, me, m, sAc + c0, eAc + c0, c1 - c0, NULL, NULL)) verdict[p] = V_TN;
+        else if (orc_interval_join(ms, me, m, sFc + f0, eFc + f0, f1 - f0, NULL, NULL)) verdict[p] = V_TH;
+        else verdict[p] = V_IND;
+        free(ms); free(me);
+    }
+    return ORC_OK;
+}
+
+/*
+ * Exact geometry for the variants' soundness checks.
+ *   orc_point_in_closed_polygon: the point lies inside or on the boundary.
+ *   orc_linestring_meets_polygon: a segment meets an edge (closed), or the
+ *   linestring's first vertex lies inside the polygon.
+ */
+int orc_point_in_closed_polygon(const double *poly, int64_t nv, double px, double py)
+{
+    int64_t *x = (int64_t *)malloc(sizeof(int64_t) * 2 * nv);
+    if (!x) return ORC_E_NOMEM;
+    int64_t *y = x + nv, X, Y;
+    int rc = lattice(px, 0.0, &X);
+    if (!rc) rc = lattice(py, 0.0, &Y);
+    for (int64_t k = 0; k < nv && !rc; k++) {
+        rc = lattice(poly[2 * k], 0.0, &x[k]);
+        if (!rc) rc = lattice(poly[2 * k + 1], 0.0, &y[k]);
+    }
+    if (rc) { free(x); return rc; }
+    int on = 0;
+    for (int64_t k = 0; k < nv && !on; k++) {
+        const int64_t k2 = (k + 1 == nv) ? 0 : k + 1;
+        on = orient(x[k], y[k], x[k2], y[k2], X, Y) == 0 && on_seg(x[k], y[k], x[k2], y[k2], X, Y);
+    }
+    const int in = on || crossing_inside(x, y, nv, NULL, nv, X, Y);
+    free(x);
+    return in;
+}
+
+int orc_linestring_meets_polygon(const double *line, int64_t nl, const double *poly, int64_t np)
+{
+    int64_t *lx = (int64_t *)malloc(sizeof(int64_t) * 2 * nl), *px = (int64_t *)malloc(sizeof(int64_t) * 2 * np);
+    if (!lx || !px) { free(lx); free(px); return ORC_E_NOMEM; }
+    int64_t *ly = lx + nl, *py = px + np;
+    int rc = ORC_OK;
+    for (int64_t k = 0; k < nl && !rc; k++) { rc = lattice(line[2 * k], 0.0, &lx[k]); if (!rc) rc = lattice(line[2 * k + 1], 0.0, &ly[k]); }
+    for (int64_t k = 0; k < np && !rc; k++) { rc = lattice(poly[2 * k], 0.0, &px[k]); if (!rc) rc = lattice(poly[2 * k + 1], 0.0, &py[k]); }
+    if (rc) { free(lx); free(px); return rc; }
+    int hit = 0;
+    for (int64_t a = 0; a + 1 < nl && !hit; a++)
+        for (int64_t b = 0; b < np && !hit; b++) {
+            const int64_t b2 = (b + 1 == np) ? 0 : b + 1;
+            hit = seg_seg(lx[a], ly[a], lx[a + 1], ly[a + 1], px[b], py[b], px[b2], py[b2]);
+        }
+    if (!hit) hit = crossing_inside(px, py, np, NULL, np, lx[0], ly[0]);
+    free(lx); free(px);
+    return hit;
+}

@@ -355,6 +355,78 @@ int april_serve_stats(april_server_t *server, april_serve_stats_t *stats);
 /* Finish batches in flight, stop the threads, free everything. */
 void april_serve_destroy(april_server_t *server);
 
+/* ------------------------------------------------------ query variants */
+/* Sec. 4.3.2-4.3.3 and 5.3: the filter with another predicate, another data
+ * type, or lists of two grid orders.  One wavefront per pair; the same
+ * verdict codes (APRIL_TN / APRIL_TH / APRIL_INDECISIVE, APRIL_BAD_PAIR for
+ * an index out of range) and count layout as april_filter_pairs; device
+ * pointers, asynchronous on `hip_stream` (a 16 KiB stream-ordered scratch
+ * when d_counts is given).  Lists must be device-resident and raw. */
+
+/*
+ * Within join (Sec. 4.3.2): is R[d_r[p]] within S[d_s[p]]?  AA-join first:
+ * no overlap -> APRIL_TN (disjoint); then every A(r) interval inside one
+ * F(s) interval -> APRIL_TH (r lies inside s); else APRIL_INDECISIVE.  No
+ * FA-join (it could only show that s is within r).
+ * Errors: APRIL_E_INVALID, APRIL_E_GRID (different grids), APRIL_E_HIP.
+ */
+int april_filter_within(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                        const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict, uint64_t *d_counts,
+                        void *hip_stream);
+
+/* Linestring approximations (Sec. 4.3.3): per linestring, the sorted ids of
+ * the cells whose closed square one of its segments meets (a linestring has
+ * only Partial cells, and its cells seldom form runs, so ids, not intervals). */
+typedef struct april_cells april_cells_t;
+
+/*
+ * Build the cell lists of n_lines linestrings on `grid` (host, multi-threaded).
+ *   xy, vtx_off  as for april_build_lists, but open chains of >= 2 vertices
+ *                (no closing segment)
+ *   flags        0 or APRIL_STRICT
+ * Errors: APRIL_E_INVALID (NULL, n_lines == 0, < 2 vertices, non-lattice
+ * under APRIL_STRICT), APRIL_E_GRID (a vertex in the outer cell ring or out
+ * of the grid), APRIL_E_NOMEM.
+ */
+int april_build_cells(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
+                      uint64_t n_lines, uint32_t flags, april_cells_t **out);
+
+/* Upload host cells (read until the stream passes the copies); free both
+ * with april_cells_free. */
+int april_cells_to_device(const april_cells_t *host, void *hip_stream, april_cells_t **out);
+/* Counts of linestrings and of cell ids. */
+int april_cells_info(const april_cells_t *cells, uint64_t *n_lines, uint64_t *n_ids);
+/* Host cells into caller arrays: off[n_lines+1], ids[n_ids]. */
+int april_cells_export(const april_cells_t *cells, uint64_t *off, uint32_t *ids);
+void april_cells_free(april_cells_t *cells);
+
+/*
+ * Polygon-linestring join (Sec. 4.3.3): for pair p, polygon P[d_p[p]] and
+ * linestring L[d_l[p]], Alg. 2's joins with the cell ids as intervals
+ * [c, c+1): A(p) against them, no overlap -> APRIL_TN; F(p) against them,
+ * an overlap -> APRIL_TH (the linestring meets a cell inside the polygon);
+ * else APRIL_INDECISIVE.
+ * Errors: APRIL_E_INVALID, APRIL_E_GRID (different grids), APRIL_E_HIP.
+ */
+int april_filter_linestrings(const april_lists_t *P, const april_cells_t *L, const uint32_t *d_p,
+                             const uint32_t *d_l, uint64_t n_pairs, uint8_t *d_verdict, uint64_t *d_counts,
+                             void *hip_stream);
+
+/*
+ * Alg. 2 across grid orders (Sec. 5.3): R and S built on grids with the
+ * same origin and side and orders NR, NS.  With NR != NS, the finer side's
+ * A-intervals are mapped to the coarser grid, a' = [a_start >> n,
+ * (a_end - 1) >> n] with n = 2 |NR - NS| (taken half-open), and only two
+ * joins run: mapped A against the coarse A-list (no overlap -> APRIL_TN),
+ * mapped A against the coarse F-list (an overlap -> APRIL_TH); else
+ * APRIL_INDECISIVE.  With NR == NS this is april_filter_pairs' verdict.
+ * Errors: APRIL_E_INVALID, APRIL_E_GRID (different data spaces or
+ * partitioned collections), APRIL_E_HIP.
+ */
+int april_filter_mixed(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                       const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict, uint64_t *d_counts,
+                       void *hip_stream);
+
 /* ---------------------------------------------------------- refinement */
 /* The step after the filter (Sec. 2): the pairs it leaves indecisive are
  * decided by an exact intersection test of the two polygons. */

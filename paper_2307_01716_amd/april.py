@@ -128,6 +128,17 @@ def lib():
     L.april_polys_free.argtypes = [P]
     L.april_polys_free.restype = None
     L.april_refine_pairs.argtypes = [P, P, P, P, u64, P, P, P, P]
+    L.april_build_cells.argtypes = [C.POINTER(april_grid_t), P, P, u64, u32, C.POINTER(P)]
+    L.april_cells_to_device.argtypes = [P, P, C.POINTER(P)]
+    L.april_cells_info.argtypes = [P, C.POINTER(u64), C.POINTER(u64)]
+    L.april_cells_export.argtypes = [P, P, P]
+    L.april_cells_free.argtypes = [P]
+    L.april_cells_free.restype = None
+    for name in ("april_filter_within", "april_filter_linestrings", "april_filter_mixed"):
+        getattr(L, name).argtypes = [P, P, P, P, u64, P, P, P]
+        getattr(L, name).restype = C.c_int
+    for name in ("april_build_cells", "april_cells_to_device", "april_cells_info", "april_cells_export"):
+        getattr(L, name).restype = C.c_int
     L.april_last_error.restype = C.c_char_p
     for name in ("april_build_lists", "april_build_lists_partitioned", "april_build_lists_gpu", "april_lists_from_arrays", "april_lists_info",
                  "april_lists_export", "april_lists_to_device", "april_lists_download",
@@ -302,6 +313,83 @@ def april_alg2_bytes(R: Lists, S: Lists, r, s, bytes_out, stream=None) -> int:
     n = int(r.numel())
     return _check(lib().april_alg2_bytes(R.handle, S.handle, _dptr(r), _dptr(s), n,
                                          _dptr(bytes_out), _stream(stream)))
+
+
+class Cells:
+    """Owning handle of linestring cell lists (host- or device-resident)."""
+
+    def __init__(self, handle: int, keep=None):
+        self._h = handle
+        self._keep = keep
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("cells were freed")
+        return self._h
+
+    def info(self):
+        n, m = C.c_uint64(), C.c_uint64()
+        _check(lib().april_cells_info(self.handle, C.byref(n), C.byref(m)))
+        return int(n.value), int(m.value)
+
+    def __len__(self):
+        return self.info()[0]
+
+    def export(self):
+        """(off, ids) numpy arrays of host cells."""
+        n, m = self.info()
+        off, ids = np.empty(n + 1, np.uint64), np.empty(m, np.uint32)
+        _check(lib().april_cells_export(self.handle, _np(off), _np(ids)))
+        return off, ids
+
+    def free(self):
+        if self._h and not _exiting:
+            lib().april_cells_free(self._h)
+        self._h = None
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def april_build_cells(grid, xy: np.ndarray, vtx_off: np.ndarray, flags: int = 0) -> Cells:
+    """Cell lists of linestrings (open chains) on `grid`; host cells."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    vo = np.ascontiguousarray(vtx_off, dtype=np.uint64)
+    g = _grid(grid)
+    h = C.c_void_p()
+    _check(lib().april_build_cells(C.byref(g), _np(xy), _np(vo), len(vo) - 1, flags, C.byref(h)))
+    return Cells(h.value)
+
+
+def april_cells_to_device(host: Cells, stream=None) -> Cells:
+    h = C.c_void_p()
+    _check(lib().april_cells_to_device(host.handle, _stream(stream), C.byref(h)))
+    return Cells(h.value, keep=host)
+
+
+def _variant(fn, A, B, a, b, verdict, counts, stream):
+    n = int(a.numel())
+    return _check(fn(A.handle, B.handle, _dptr(a), _dptr(b), n, _dptr(verdict), _dptr(counts), _stream(stream)))
+
+
+def april_filter_within(R: Lists, S: Lists, r, s, verdict, counts=None, stream=None) -> int:
+    """Within-join filter: is R[r[i]] within S[s[i]]? (device tensors)"""
+    return _variant(lib().april_filter_within, R, S, r, s, verdict, counts, stream)
+
+
+def april_filter_linestrings(P: Lists, L: Cells, p, l, verdict, counts=None, stream=None) -> int:
+    """Polygon-linestring filter on device lists and device cells."""
+    return _variant(lib().april_filter_linestrings, P, L, p, l, verdict, counts, stream)
+
+
+def april_filter_mixed(R: Lists, S: Lists, r, s, verdict, counts=None, stream=None) -> int:
+    """Alg. 2 across grid orders (same data space)."""
+    return _variant(lib().april_filter_mixed, R, S, r, s, verdict, counts, stream)
 
 
 class Polys:

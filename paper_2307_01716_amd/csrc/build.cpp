@@ -57,6 +57,9 @@ public:
     void set_grid(const LatticeGrid &g) { g_ = g; }
 
     int run(const Poly &p, Result &out);
+    // the sorted, distinct ids of the cells the open chain p meets (its
+    // segments only; no closing edge)
+    void chain_cells(const Poly &p, std::vector<uint64_t> &ids);
     // the same lists, with the steps split over `threads` threads (for one
     // large polygon)
     int run_parallel(const Poly &p, Result &out, int threads);
@@ -225,6 +228,15 @@ void Builder::intervalize(const uint8_t *cls, size_t m, Result &out) const {
         }                                                                                   \
         return c;                                                                           \
     })(t)
+
+void Builder::chain_cells(const Poly &p, std::vector<uint64_t> &ids) {
+    touched_.clear();
+    for (size_t k = 0; k + 1 < p.x.size(); k++) edge_cells(p.x[k], p.y[k], p.x[k + 1], p.y[k + 1], touched_);
+    ids.clear();
+    for (uint64_t t : touched_) ids.push_back(t >> 1);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+}
 
 int Builder::run(const Poly &p, Result &out) {
     const size_t nv = p.x.size();
@@ -543,4 +555,80 @@ extern "C" int april_build_lists_partitioned(const april_grid_t *grids, uint32_t
     desc.flags = APRIL_GRID_PARTITIONED;
     return build_collection(lg, [&](uint64_t k) { return grid_of[k]; }, desc, key, xy, vtx_off, n, flags,
                             out, host_threads());
+}
+
+extern "C" int april_build_cells(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off, uint64_t n,
+                                 uint32_t flags, april_cells_t **out) {
+    clear_error();
+    if (!grid || !xy || !vtx_off || !out) return fail(APRIL_E_INVALID, "NULL argument");
+    if (n == 0) return fail(APRIL_E_INVALID, "no linestrings");
+    if (flags & ~APRIL_STRICT) return fail(APRIL_E_INVALID, "unknown flags");
+    LatticeGrid g;
+    if (int rc = lattice_grid(grid, &g)) return rc;
+    for (uint64_t k = 0; k < n; k++)
+        if (vtx_off[k + 1] < vtx_off[k] + 2) return fail(APRIL_E_INVALID, "linestring with < 2 vertices");
+    const bool strict = flags & APRIL_STRICT;
+    std::vector<std::vector<uint32_t>> per(n);
+    std::atomic<uint64_t> next{0};
+    std::atomic<int> err{0};
+    std::atomic<uint64_t> bad{~0ull};
+    const int T = int(std::min<uint64_t>(uint64_t(host_threads()), n));
+    parallel(T, [&](int) {
+        Builder b(g);
+        Poly p;
+        std::vector<uint64_t> ids;
+        for (;;) {
+            const uint64_t k = next.fetch_add(1);
+            if (k >= n || err.load()) break;
+            p.x.clear();
+            p.y.clear();
+            int rc = APRIL_OK;
+            for (uint64_t v = vtx_off[k]; v < vtx_off[k + 1] && rc == APRIL_OK; v++) {
+                int64_t c[2];
+                for (int a = 0; a < 2 && rc == APRIL_OK; a++) {
+                    const double q = (xy[2 * v + a] - (a ? g.y0 : g.x0)) * 1073741824.0;
+                    const double r = std::nearbyint(q);
+                    if (!(std::fabs(r) < 4.0e15)) rc = APRIL_E_GRID;
+                    else if (strict && r != q) rc = APRIL_E_INVALID;
+                    else c[a] = int64_t(r);
+                }
+                if (rc == APRIL_OK &&
+                    (c[0] <= g.w || c[1] <= g.w || c[0] >= (g.cells - 1) * g.w || c[1] >= (g.cells - 1) * g.w))
+                    rc = APRIL_E_GRID;
+                if (rc == APRIL_OK) {
+                    p.x.push_back(c[0]);
+                    p.y.push_back(c[1]);
+                }
+            }
+            if (rc != APRIL_OK) {
+                int z = 0;
+                err.compare_exchange_strong(z, rc);
+                bad.store(k);
+                break;
+            }
+            b.chain_cells(p, ids);
+            per[k].assign(ids.begin(), ids.end());
+        }
+    });
+    if (int rc = err.load())
+        return fail(rc, "linestring " + std::to_string(bad.load()) +
+                            (rc == APRIL_E_GRID ? " reaches the outer cell ring or leaves the grid"
+                                                : " has a non-lattice coordinate"));
+    auto *C = new (std::nothrow) april_cells;
+    if (!C) return fail(APRIL_E_NOMEM, "out of host memory");
+    try {
+        C->grid = *grid;
+        C->n = n;
+        C->off.resize(n + 1);
+        C->off[0] = 0;
+        for (uint64_t k = 0; k < n; k++) C->off[k + 1] = C->off[k] + per[k].size();
+        C->n_ids = C->off[n];
+        C->ids.resize(C->n_ids);
+        for (uint64_t k = 0; k < n; k++) std::copy(per[k].begin(), per[k].end(), C->ids.begin() + C->off[k]);
+    } catch (...) {
+        delete C;
+        return fail(APRIL_E_NOMEM, "out of host memory");
+    }
+    *out = C;
+    return APRIL_OK;
 }

@@ -70,6 +70,19 @@ struct april_lists {
     april::DeviceArrays d;
 };
 
+// Linestring cell lists (Sec. 4.3.3): per linestring the sorted ids of the
+// cells its segments meet.
+struct april_cells {
+    april_grid_t grid{};
+    uint64_t n = 0, n_ids = 0;
+    int device = -1;                 // -1: host
+    std::vector<uint64_t> off;       // host copy
+    std::vector<uint32_t> ids;
+    uint64_t *d_off = nullptr;       // device copy (one allocation)
+    uint32_t *d_ids = nullptr;
+    void *d_block = nullptr;
+};
+
 namespace april {
 
 bool same_grid(const april_grid_t &a, const april_grid_t &b);

@@ -1,0 +1,287 @@
+// The filter's query variants on the GPU:
+//   within joins (Sec. 4.3.2): AA, then "every A(r) interval inside one
+//     F(s) interval" -> r within s;
+//   polygon-linestring joins (Sec. 4.3.3): A(p) and F(p) against the
+//     linestring's cell ids taken as intervals [c, c+1);
+//   different granularity (Sec. 5.3): the finer side's A-intervals mapped to
+//     the coarser grid, a' = [a_s >> n, ((a_e - 1) >> n) + 1) (the paper's
+//     inclusive end in half-open form), then AA and the coarse side's F only.
+//
+// One wave per pair, pairs dealt to waves in order (wave w takes pairs
+// w, w + W, ...).  Each join streams one list, 64 elements per step, one per
+// lane, and each lane binary-searches the other (sorted, disjoint) list for
+// the first interval ending after its element starts: its element overlaps
+// the list iff that interval starts before the element ends, and lies inside
+// it iff that interval also starts at or before the element and ends at or
+// after it.  A ballot per step ends a join on its first decisive element.
+// Streaming the mapped side of a mixed-order pair keeps the searched side
+// sorted and disjoint (mapped intervals may touch or overlap each other).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace april {
+namespace {
+
+struct VList {
+    const uint32_t *s, *e;   // interval starts / ends; e == nullptr: cell ids, e = s + 1
+    uint32_t n;
+};
+
+enum Mode : uint32_t { kWithin = 0, kLinestring = 1, kMixed = 2 };
+
+struct VArgs {
+    // R side (within: r; linestring: polygons; mixed: R)
+    const uint64_t *offAr, *offFr;
+    const uint32_t *sAr, *eAr, *sFr, *eFr;
+    // S side (within: s; linestring: the cells; mixed: S)
+    const uint64_t *offAs, *offFs;
+    const uint32_t *sAs, *eAs, *sFs, *eFs;
+    const uint32_t *r, *s;
+    uint64_t n_pairs, n_r, n_s;
+    uint8_t *verdict;
+    unsigned int *ctr;   // count slots (totals), or nullptr
+    uint32_t shift_r, shift_s;   // mixed: bits to drop from R's / S's A-intervals (one of them is 0)
+};
+
+__device__ __forceinline__ uint32_t gl(const uint32_t *p, uint64_t i) {
+    return ((const uint32_t __attribute__((address_space(1))) *)p)[i];
+}
+
+// first interval of X with end > y0 (X sorted, disjoint), as an index in [0, n]
+__device__ __forceinline__ uint32_t first_ending_after(const VList &X, uint32_t y0) {
+    uint32_t lo = 0, hi = X.n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint32_t e = X.e ? gl(X.e, mid) : gl(X.s, mid) + 1;
+        if (e <= y0) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void element(const VList &Y, uint32_t j, uint32_t shift, uint32_t &y0, uint32_t &y1) {
+    const uint32_t s = gl(Y.s, j), e = Y.e ? gl(Y.e, j) : s + 1;
+    y0 = s >> shift;
+    y1 = ((e - 1) >> shift) + 1;
+}
+
+// Does any element of Y (mapped by `shift`) overlap X?  Whole wave.
+__device__ bool any_overlap(const VList &X, const VList &Y, uint32_t shift, uint32_t lane) {
+    if (X.n == 0) return false;
+    for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        bool h = false;
+        if (j < Y.n) {
+            uint32_t y0, y1;
+            element(Y, j, shift, y0, y1);
+            const uint32_t i = first_ending_after(X, y0);
+            h = i < X.n && gl(X.s, i) < y1;
+        }
+        if (__any(h)) return true;
+    }
+    return false;
+}
+
+// Does every element of Y lie inside one interval of X?  Whole wave.
+__device__ bool all_inside(const VList &X, const VList &Y, uint32_t lane) {
+    for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        bool miss = false;
+        if (j < Y.n) {
+            uint32_t y0, y1;
+            element(Y, j, 0, y0, y1);
+            const uint32_t i = first_ending_after(X, y0);
+            miss = !(i < X.n && gl(X.s, i) <= y0 && y1 <= gl(X.e, i));
+        }
+        if (__any(miss)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ VList list_of(const uint64_t *off, const uint32_t *s, const uint32_t *e, uint32_t k) {
+    const uint64_t a = ((const uint64_t __attribute__((address_space(1))) *)off)[k];
+    const uint64_t b = ((const uint64_t __attribute__((address_space(1))) *)off)[k + 1];
+    return VList{s + a, e ? e + a : nullptr, uint32_t(b - a)};
+}
+
+template <uint32_t MODE>
+__global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t waves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
+    for (uint64_t p = wave; p < a.n_pairs; p += waves) {
+        const uint32_t r = uniform(gl(a.r, p)), s = uniform(gl(a.s, p));
+        uint8_t v;
+        if (r >= a.n_r || s >= a.n_s) {
+            v = APRIL_BAD_PAIR;
+        } else if (MODE == kWithin) {
+            const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r);
+            const VList As = list_of(a.offAs, a.sAs, a.eAs, s), Fs = list_of(a.offFs, a.sFs, a.eFs, s);
+            v = !any_overlap(As, Ar, 0, lane) ? APRIL_TN : all_inside(Fs, Ar, lane) ? APRIL_TH : APRIL_INDECISIVE;
+        } else if (MODE == kLinestring) {
+            const VList Ap = list_of(a.offAr, a.sAr, a.eAr, r), Fp = list_of(a.offFr, a.sFr, a.eFr, r);
+            const VList Cl = list_of(a.offAs, a.sAs, nullptr, s);
+            v = !any_overlap(Ap, Cl, 0, lane) ? APRIL_TN : any_overlap(Fp, Cl, 0, lane) ? APRIL_TH
+                                                                                      : APRIL_INDECISIVE;
+        } else {
+            const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r), Fr = list_of(a.offFr, a.sFr, a.eFr, r);
+            const VList As = list_of(a.offAs, a.sAs, a.eAs, s), Fs = list_of(a.offFs, a.sFs, a.eFs, s);
+            if (a.shift_r == 0 && a.shift_s == 0) {   // one order: Alg. 2 unchanged
+                v = !any_overlap(As, Ar, 0, lane)                                   ? APRIL_TN
+                    : any_overlap(Fs, Ar, 0, lane) || any_overlap(As, Fr, 0, lane) ? APRIL_TH
+                                                                                     : APRIL_INDECISIVE;
+            } else if (a.shift_r) {                   // R finer: stream its mapped A
+                v = !any_overlap(As, Ar, a.shift_r, lane) ? APRIL_TN
+                    : any_overlap(Fs, Ar, a.shift_r, lane) ? APRIL_TH
+                                                           : APRIL_INDECISIVE;
+            } else {                                  // S finer
+                v = !any_overlap(Ar, As, a.shift_s, lane) ? APRIL_TN
+                    : any_overlap(Fr, As, a.shift_s, lane) ? APRIL_TH
+                                                           : APRIL_INDECISIVE;
+            }
+        }
+        if (lane == 0) {
+            a.verdict[p] = v;
+            c_tn += v == APRIL_TN;
+            c_th += v == APRIL_TH;
+            c_ind += v == APRIL_INDECISIVE;
+        }
+    }
+    if (a.ctr && lane == 0) {
+        const unsigned long long t[3] = {c_tn, c_th, c_ind};
+        add_totals(a.ctr, uint32_t(wave), t, 3);
+    }
+}
+
+int launch_variant(uint32_t mode, VArgs a, unsigned long long *counts, hipStream_t stream) {
+    DeviceState *st = nullptr;
+    if (int rc = device_state(&st)) return rc;
+    void *ws = nullptr;
+    if (counts) {
+        hipError_t e = hipMallocAsync(&ws, kCtrBytes, stream);
+        if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("variant scratch: ") + hipGetErrorString(e));
+        a.ctr = static_cast<unsigned int *>(ws);
+        k_zero_ctrs<<<1, 64, 0, stream>>>(a.ctr);
+    } else {
+        a.ctr = nullptr;
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && a.n_pairs) {
+        const uint64_t waves = std::min<uint64_t>(a.n_pairs, uint64_t(st->cus) * 32);
+        const uint32_t blocks = uint32_t((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+        switch (mode) {
+            case kWithin: k_variant<kWithin><<<blocks, kBlock, 0, stream>>>(a); break;
+            case kLinestring: k_variant<kLinestring><<<blocks, kBlock, 0, stream>>>(a); break;
+            default: k_variant<kMixed><<<blocks, kBlock, 0, stream>>>(a); break;
+        }
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && counts) {
+        k_sum_totals<<<1, 64, 0, stream>>>(a.ctr, counts, 3);
+        e = hipGetLastError();
+    }
+    if (ws) APRIL_HIP_TRY(hipFreeAsync(ws, stream));
+    if (e != hipSuccess) return fail(APRIL_E_HIP, std::string("variant launch: ") + hipGetErrorString(e));
+    return APRIL_OK;
+}
+
+int check_device(const april_lists_t *L) {
+    if (!L) return fail(APRIL_E_INVALID, "NULL lists");
+    if (L->device < 0) return fail(APRIL_E_INVALID, "lists must be on a device");
+    if (L->codec != APRIL_CODEC_RAW) return fail(APRIL_E_INVALID, "query variants take raw lists");
+    int cur = 0;
+    APRIL_HIP_TRY(hipGetDevice(&cur));
+    if (cur != L->device) return fail(APRIL_E_INVALID, "current device does not hold the lists");
+    return APRIL_OK;
+}
+
+VArgs base_args(const april_lists_t *R, const uint32_t *d_r, const uint32_t *d_s, uint64_t n, uint8_t *d_v) {
+    VArgs a{};
+    a.offAr = R->d.off_a;
+    a.offFr = R->d.off_f;
+    a.sAr = R->d.start_a;
+    a.eAr = R->d.end_a;
+    a.sFr = R->d.start_f;
+    a.eFr = R->d.end_f;
+    a.r = d_r;
+    a.s = d_s;
+    a.n_pairs = n;
+    a.n_r = R->n;
+    a.verdict = d_v;
+    return a;
+}
+
+void set_s(VArgs &a, const april_lists_t *S) {
+    a.offAs = S->d.off_a;
+    a.offFs = S->d.off_f;
+    a.sAs = S->d.start_a;
+    a.eAs = S->d.end_a;
+    a.sFs = S->d.start_f;
+    a.eFs = S->d.end_f;
+    a.n_s = S->n;
+}
+
+}  // namespace
+}  // namespace april
+
+using namespace april;
+
+extern "C" int april_filter_within(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                                   const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
+                                   uint64_t *d_counts, void *hip_stream) {
+    clear_error();
+    if (int rc = check_device(R)) return rc;
+    if (int rc = check_device(S)) return rc;
+    if (R->device != S->device) return fail(APRIL_E_INVALID, "lists on different devices");
+    if (!same_grid(R->grid, S->grid) || R->partition_key != S->partition_key)
+        return fail(APRIL_E_GRID, "R and S lists use different grids");
+    if (n_pairs && (!d_r || !d_s || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
+    VArgs a = base_args(R, d_r, d_s, n_pairs, d_verdict);
+    set_s(a, S);
+    return launch_variant(kWithin, a, reinterpret_cast<unsigned long long *>(d_counts),
+                          static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" int april_filter_linestrings(const april_lists_t *P, const april_cells_t *L, const uint32_t *d_p,
+                                        const uint32_t *d_l, uint64_t n_pairs, uint8_t *d_verdict,
+                                        uint64_t *d_counts, void *hip_stream) {
+    clear_error();
+    if (int rc = check_device(P)) return rc;
+    if (!L) return fail(APRIL_E_INVALID, "NULL cells");
+    if (L->device != P->device) return fail(APRIL_E_INVALID, "cells must be on the lists' device");
+    if (!same_grid(P->grid, L->grid) || P->partition_key != 0)
+        return fail(APRIL_E_GRID, "polygons and linestrings use different grids");
+    if (n_pairs && (!d_p || !d_l || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
+    VArgs a = base_args(P, d_p, d_l, n_pairs, d_verdict);
+    a.offAs = L->d_off;
+    a.sAs = L->d_ids;
+    a.n_s = L->n;
+    return launch_variant(kLinestring, a, reinterpret_cast<unsigned long long *>(d_counts),
+                          static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" int april_filter_mixed(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                                  const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict, uint64_t *d_counts,
+                                  void *hip_stream) {
+    clear_error();
+    if (int rc = check_device(R)) return rc;
+    if (int rc = check_device(S)) return rc;
+    if (R->device != S->device) return fail(APRIL_E_INVALID, "lists on different devices");
+    const april_grid_t &g = R->grid, &h = S->grid;
+    if (g.x0 != h.x0 || g.y0 != h.y0 || g.side != h.side || g.flags != h.flags || R->partition_key ||
+        S->partition_key)
+        return fail(APRIL_E_GRID, "R and S must cover one data space (same origin and side)");
+    if (n_pairs && (!d_r || !d_s || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
+    VArgs a = base_args(R, d_r, d_s, n_pairs, d_verdict);
+    set_s(a, S);
+    a.shift_r = g.order > h.order ? 2 * (g.order - h.order) : 0;
+    a.shift_s = h.order > g.order ? 2 * (h.order - g.order) : 0;
+    return launch_variant(kMixed, a, reinterpret_cast<unsigned long long *>(d_counts),
+                          static_cast<hipStream_t>(hip_stream));
+}

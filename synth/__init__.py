@@ -17,3 +17,4 @@ from .grid import Grid, grid_covering  # noqa: F401
 from .intervals import random_lists, complement_list, sub_lists, ListSet  # noqa: F401
 from . import configs  # noqa: F401
 from . import partitions  # noqa: F401
+from . import linestrings  # noqa: F401

@@ -11,8 +11,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .grid import grid_covering
-from .polygons import PolygonSet, star_polygons
+from .grid import Grid, grid_covering
+from .polygons import LATTICE, PolygonSet, star_polygons
 
 
 def tiny(k: int = 1, n: int = 1000):
@@ -125,3 +125,28 @@ def partitioned(k: int = 4, n: int = 500_000, parts: int = 16, order: int = 16):
     R = scale_collection(np.random.default_rng(1000 * k + 1), n, k)
     S = scale_collection(np.random.default_rng(1000 * k + 2), n, k)
     return R, S, layout(R, S, parts, order)
+
+
+def linestring_scale(k: int = 6, n_poly: int = 200_000, n_lines: int = 200_000, order: int = 16):
+    """Polygon-linestring workload: the at-scale polygon collection and
+    n_lines random-walk linestrings starting like the polygon centres."""
+    from .linestrings import random_walks
+    P = scale_collection(np.random.default_rng(1000 * k + 1), n_poly, 2)
+    rng = np.random.default_rng(1000 * k + 2)
+    starts = gmm_centres_shared(_mixture_rng(2), rng, n_lines, SCALE_SIGMA)
+    lo, hi = P.xy.min(axis=0), P.xy.max(axis=0)
+    L = random_walks(rng, starts, lo, hi)
+    return P, L, grid_covering([P, L], order)
+
+
+def two_orders(R, S, fine: int = 16, coarse: int = 14):
+    """One data space at two grid orders: a coarse grid over both sets
+    (guard ring of two coarse cells, cell side divisible by 2^(fine-coarse))
+    and the fine grid with the same origin and side."""
+    lo = np.round(np.minimum(R.xy.min(0), S.xy.min(0)) / LATTICE).astype(np.int64)
+    hi = np.round(np.maximum(R.xy.max(0), S.xy.max(0)) / LATTICE).astype(np.int64)
+    q = 1 << (fine - coarse)
+    w = (int((hi - lo).max()) // ((1 << coarse) - 4) + 1 + q - 1) // q * q
+    x0, y0 = (lo - 2 * w) * LATTICE
+    gc = Grid(float(x0), float(y0), float(w * (1 << coarse)) * LATTICE, coarse)
+    return Grid(gc.x0, gc.y0, gc.side, fine), gc

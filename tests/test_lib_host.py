@@ -242,3 +242,25 @@ def test_parallel_builder_large_polygon_equals_sequential():
     na, nf = int(both[0][1]), int(both[3][1])
     assert np.array_equal(got[1], both[1][:na]) and np.array_equal(got[2], both[2][:na])
     assert np.array_equal(got[4], both[4][:nf]) and np.array_equal(got[5], both[5][:nf])
+
+
+def test_cells_builder_matches_oracle():
+    """Linestring cell lists (Sec. 4.3.3): the library's host builder (exact
+    edge traversal) equals the oracle's brute force, and rejects the same
+    inputs."""
+    from synth.polygons import LATTICE, PolygonSet
+    P, L, g = synth.configs.linestring_scale(n_poly=300, n_lines=800)
+    C = april.april_build_cells(g, L.xy, L.voff, april.STRICT)
+    off, ids = C.export()
+    O = oracle.build_cells(g, L)
+    assert np.array_equal(off, O.off) and np.array_equal(ids, O.ids)
+    assert C.info() == (len(L), len(O.ids))
+    # a vertex in the outer ring; a single-vertex linestring
+    bad = PolygonSet(np.array([[g.x0 + LATTICE, g.y0 + LATTICE], [g.x0 + 0.5, g.y0 + 0.5]]), np.array([0, 2]))
+    with pytest.raises(april.AprilError) as e:
+        april.april_build_cells(g, bad.xy, bad.voff, april.STRICT)
+    assert e.value.code == april.E_GRID
+    one = PolygonSet(L.xy[:1].copy(), np.array([0, 1]))
+    with pytest.raises(april.AprilError) as e:
+        april.april_build_cells(g, one.xy, one.voff, april.STRICT)
+    assert e.value.code == april.E_INVALID

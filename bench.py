@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--partitioned", action="store_true",
                     help="partitioned join, raw and compressed lists (own JSON line)")
     ap.add_argument("--part-objects", type=int, default=500_000)
+    ap.add_argument("--variants", action="store_true",
+                    help="within join, polygon-linestring join and mixed grid orders (own JSON line)")
     ap.add_argument("--build", action="store_true",
                     help="list construction on the GPU against the host builder (own JSON line)")
     ap.add_argument("--refine", action="store_true",
@@ -285,6 +287,106 @@ def partitioned_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def variants_bench(args):
+    """The filter's query variants at scale, each over all its candidate
+    pairs with lists resident in HBM; W untimed launches, then K timed ones,
+    HIP events on the launch stream:
+      within       r within s on the at-scale join (4.7M pairs);
+      linestrings  200k polygons x 200k random-walk linestrings;
+      mixed        R at grid order 16 against S at order 14 (one data space).
+    The same pairs through april_filter_pairs (one order) are timed beside
+    for reference.  The CPU baseline is the oracle's within filter on a
+    bounded sample."""
+    import torch
+
+    import synth
+    from paper_2307_01716_amd import april
+
+    assert torch.cuda.is_available(), "no HIP device"
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    def dev(h):
+        return april.april_lists_to_device(h, stream=stream)
+
+    forms = {}
+    R, S, g = synth.configs.scale()
+    hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
+    hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
+    r_np, s_np = april.april_mbr_join(R.mbrs(), S.mbrs())
+    P = len(r_np)
+    r = torch.from_numpy(r_np.view(np.int32)).cuda()
+    s = torch.from_numpy(s_np.view(np.int32)).cuda()
+    v = torch.empty(P, dtype=torch.uint8, device="cuda")
+    c = torch.zeros(3, dtype=torch.int64, device="cuda")
+    dR, dS = dev(hR), dev(hS)
+    for name, fn in (("within", lambda: april.april_filter_within(dR, dS, r, s, v, c, stream=stream)),
+                     ("one-order filter (plain)", lambda: april.april_filter_pairs(dR, dS, r, s, v, c,
+                                                                                    stream=stream))):
+        ms = timed(fn)
+        cc = c.cpu().numpy()
+        forms[name] = {"ms": ms, "pairs": P, "pairs_per_s": P / (ms / 1e3),
+                       "verdicts": {"TN": int(cc[0]), "TH": int(cc[1]), "IND": int(cc[2])}}
+        log(f"{name}: {ms:.3f} ms, {P / ms / 1e6:.3f} G pairs/s, TN/TH/IND = {cc.tolist()}")
+    gf, gc = synth.configs.two_orders(R, S, 16, 14)
+    mR = dev(april.april_build_lists(gf, R.xy, R.voff, april.STRICT))
+    mS = dev(april.april_build_lists(gc, S.xy, S.voff, april.STRICT))
+    ms = timed(lambda: april.april_filter_mixed(mR, mS, r, s, v, c, stream=stream))
+    cc = c.cpu().numpy()
+    forms["mixed 16 x 14"] = {"ms": ms, "pairs": P, "pairs_per_s": P / (ms / 1e3),
+                              "verdicts": {"TN": int(cc[0]), "TH": int(cc[1]), "IND": int(cc[2])},
+                              "device_bytes_S": int(mS.info().device_bytes),
+                              "device_bytes_S_order16": int(dS.info().device_bytes)}
+    log(f"mixed 16 x 14: {ms:.3f} ms, {P / ms / 1e6:.3f} G pairs/s, TN/TH/IND = {cc.tolist()}; "
+        f"S lists {mS.info().device_bytes / 1e6:.0f} MB at order 14 vs {dS.info().device_bytes / 1e6:.0f} MB")
+    del mR, mS
+    Pp, L, gl = synth.configs.linestring_scale()
+    dP = dev(april.april_build_lists(gl, Pp.xy, Pp.voff, april.STRICT))
+    hC = april.april_build_cells(gl, L.xy, L.voff, april.STRICT)
+    dC = april.april_cells_to_device(hC, stream=stream)
+    p_np, l_np = april.april_mbr_join(Pp.mbrs(), L.mbrs())
+    pl = torch.from_numpy(p_np.view(np.int32)).cuda()
+    ll = torch.from_numpy(l_np.view(np.int32)).cuda()
+    vl = torch.empty(len(p_np), dtype=torch.uint8, device="cuda")
+    ms = timed(lambda: april.april_filter_linestrings(dP, dC, pl, ll, vl, c, stream=stream))
+    cc = c.cpu().numpy()
+    forms["linestrings"] = {"ms": ms, "pairs": int(len(p_np)), "pairs_per_s": len(p_np) / (ms / 1e3),
+                            "cells": int(hC.info()[1]),
+                            "verdicts": {"TN": int(cc[0]), "TH": int(cc[1]), "IND": int(cc[2])}}
+    log(f"linestrings: {ms:.3f} ms for {len(p_np)} pairs, {len(p_np) / ms / 1e6:.3f} G pairs/s, "
+        f"TN/TH/IND = {cc.tolist()}")
+    out = {"metric": "candidate pairs filtered/s (within join at scale)", "value": forms["within"]["pairs_per_s"],
+           "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": forms["within"]["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "scale: 200k x 200k star polygons, grid 2^16, all MBR candidate pairs; "
+                                  "linestrings: 200k polygons x 200k random walks"},
+           "forms": forms}
+    if not args.no_cpu_baseline:
+        import oracle
+        LRo, LSo = oracle.Lists(*hR.export()), oracle.Lists(*hS.export())
+        sample = np.arange(0, P, 10)
+        t0 = time.perf_counter()
+        oracle.filter_within(LRo, LSo, r_np[sample], s_np[sample])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(sample) / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+                               "sample": f"every 10th within pair ({len(sample)}), one thread ({dt:.1f} s)"}
+        log(f"cpu baseline (within): {len(sample) / dt / 1e6:.2f} M pairs/s on one thread")
+    print(json.dumps(out), flush=True)
+
+
 def build_bench(args):
     """List construction (Sec. 6) on the GPU against the library's host
     builder, on the at-scale collection R (200k polygons) and on 200 complex
@@ -487,6 +589,9 @@ def main():
         return
     if args.build:
         build_bench(args)
+        return
+    if args.variants:
+        variants_bench(args)
         return
     if args.partitioned:
         if args.copy_calibration:

@@ -2,20 +2,23 @@
 //   within joins (Sec. 4.3.2): AA, then "every A(r) interval inside one
 //     F(s) interval" -> r within s;
 //   polygon-linestring joins (Sec. 4.3.3): A(p) and F(p) against the
-//     linestring's cell ids taken as intervals [c, c+1);
+//     linestring's cell ids taken as intervals [c, c+1) (here the cells are
+//     searched and the polygon's lists streamed);
 //   different granularity (Sec. 5.3): the finer side's A-intervals mapped to
 //     the coarser grid, a' = [a_s >> n, ((a_e - 1) >> n) + 1) (the paper's
 //     inclusive end in half-open form), then AA and the coarse side's F only.
 //
 // One wave per pair, pairs dealt to waves in order (wave w takes pairs
-// w, w + W, ...).  Each join streams one list, 64 elements per step, one per
-// lane, and each lane binary-searches the other (sorted, disjoint) list for
-// the first interval ending after its element starts: its element overlaps
-// the list iff that interval starts before the element ends, and lies inside
-// it iff that interval also starts at or before the element and ends at or
-// after it.  A ballot per step ends a join on its first decisive element.
-// Streaming the mapped side of a mixed-order pair keeps the searched side
-// sorted and disjoint (mapped intervals may touch or overlap each other).
+// w, w + W, ...).  One object's A- and F-lists are made searchable (copied
+// into the wave's LDS when both hold at most 256 intervals, else read from
+// global memory); the other object's list is streamed, 64 elements per step,
+// one per lane, and each lane binary-searches for the first interval ending
+// after its element starts: its element overlaps the list iff that interval
+// starts before the element ends, and lies inside it iff that interval also
+// starts at or before the element and ends at or after it.  A ballot per
+// step ends a join on its first decisive element.  Streaming the mapped side
+// of a mixed-order pair keeps the searched side sorted and disjoint (mapped
+// intervals may touch or overlap each other).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,13 +55,23 @@ __device__ __forceinline__ uint32_t gl(const uint32_t *p, uint64_t i) {
     return ((const uint32_t __attribute__((address_space(1))) *)p)[i];
 }
 
-// first interval of X with end > y0 (X sorted, disjoint), as an index in [0, n]
-__device__ __forceinline__ uint32_t first_ending_after(const VList &X, uint32_t y0) {
-    uint32_t lo = 0, hi = X.n;
+// The searched object's lists, in LDS when both fit a tile of kTile
+// intervals (one load round per pair), else read from global memory.
+constexpr uint32_t kTile = 256;
+
+struct Res {
+    const uint32_t *as, *ae, *fs, *fe;   // LDS copies (lds) or global lists
+    uint32_t na, nf;
+    bool lds;
+};
+
+// first interval with end > y0 among n sorted, disjoint intervals (ends e)
+template <bool LDS>
+__device__ __forceinline__ uint32_t first_ending_after(const uint32_t *e, uint32_t n, uint32_t y0) {
+    uint32_t lo = 0, hi = n;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        const uint32_t e = X.e ? gl(X.e, mid) : gl(X.s, mid) + 1;
-        if (e <= y0) lo = mid + 1;
+        if ((LDS ? e[mid] : gl(e, mid)) <= y0) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -70,37 +83,79 @@ __device__ __forceinline__ void element(const VList &Y, uint32_t j, uint32_t shi
     y1 = ((e - 1) >> shift) + 1;
 }
 
-// Does any element of Y (mapped by `shift`) overlap X?  Whole wave.
-__device__ bool any_overlap(const VList &X, const VList &Y, uint32_t shift, uint32_t lane) {
-    if (X.n == 0) return false;
+template <bool LDS>
+__device__ __forceinline__ bool overlaps(const uint32_t *xs, const uint32_t *xe, uint32_t n, uint32_t y0,
+                                         uint32_t y1) {
+    const uint32_t i = first_ending_after<LDS>(xe, n, y0);
+    return i < n && (LDS ? xs[i] : gl(xs, i)) < y1;
+}
+
+template <bool LDS>
+__device__ __forceinline__ bool inside(const uint32_t *xs, const uint32_t *xe, uint32_t n, uint32_t y0, uint32_t y1) {
+    const uint32_t i = first_ending_after<LDS>(xe, n, y0);
+    return i < n && (LDS ? xs[i] : gl(xs, i)) <= y0 && y1 <= (LDS ? xe[i] : gl(xe, i));
+}
+
+// Does any element of Y (mapped by `shift`) overlap the resident A (f =
+// false) or F list?  Whole wave.
+__device__ bool any_overlap(const Res &x, bool f, const VList &Y, uint32_t shift, uint32_t lane) {
+    const uint32_t *xs = f ? x.fs : x.as, *xe = f ? x.fe : x.ae;
+    const uint32_t n = f ? x.nf : x.na;
+    if (n == 0) return false;
     for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
         const uint32_t j = j0 + lane;
         bool h = false;
         if (j < Y.n) {
             uint32_t y0, y1;
             element(Y, j, shift, y0, y1);
-            const uint32_t i = first_ending_after(X, y0);
-            h = i < X.n && gl(X.s, i) < y1;
+            h = x.lds ? overlaps<true>(xs, xe, n, y0, y1) : overlaps<false>(xs, xe, n, y0, y1);
         }
         if (__any(h)) return true;
     }
     return false;
 }
 
-// Does every element of Y lie inside one interval of X?  Whole wave.
-__device__ bool all_inside(const VList &X, const VList &Y, uint32_t lane) {
+// Does every element of Y lie inside one interval of the resident F list?
+__device__ bool all_inside_f(const Res &x, const VList &Y, uint32_t lane) {
     for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
         const uint32_t j = j0 + lane;
         bool miss = false;
         if (j < Y.n) {
             uint32_t y0, y1;
             element(Y, j, 0, y0, y1);
-            const uint32_t i = first_ending_after(X, y0);
-            miss = !(i < X.n && gl(X.s, i) <= y0 && y1 <= gl(X.e, i));
+            miss = !(x.lds ? inside<true>(x.fs, x.fe, x.nf, y0, y1) : inside<false>(x.fs, x.fe, x.nf, y0, y1));
         }
         if (__any(miss)) return false;
     }
     return true;
+}
+
+// Does any interval of Y overlap a cell of the sorted cell-id list C (as
+// [c, c+1))?  The first cell >= y0 decides for element [y0, y1).  C is in
+// LDS (cells_lds) or global memory.  Whole wave.
+template <bool LDS>
+__device__ __forceinline__ bool cell_hit(const uint32_t *c, uint32_t n, uint32_t y0, uint32_t y1) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((LDS ? c[mid] : gl(c, mid)) < y0) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < n && (LDS ? c[lo] : gl(c, lo)) < y1;
+}
+
+__device__ bool any_cell_overlap(const uint32_t *c, uint32_t n, bool in_lds, const VList &Y, uint32_t lane) {
+    if (n == 0) return false;
+    for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        bool h = false;
+        if (j < Y.n) {
+            const uint32_t y0 = gl(Y.s, j), y1 = gl(Y.e, j);
+            h = in_lds ? cell_hit<true>(c, n, y0, y1) : cell_hit<false>(c, n, y0, y1);
+        }
+        if (__any(h)) return true;
+    }
+    return false;
 }
 
 __device__ __forceinline__ VList list_of(const uint64_t *off, const uint32_t *s, const uint32_t *e, uint32_t k) {
@@ -109,9 +164,43 @@ __device__ __forceinline__ VList list_of(const uint64_t *off, const uint32_t *s,
     return VList{s + a, e ? e + a : nullptr, uint32_t(b - a)};
 }
 
+// Make an object's A and F lists searchable: copied into this wave's LDS
+// (layout A.start | A.end | F.start | F.end, kTile words each) when both
+// fit, else left in global memory.
+__device__ Res stage(const VList &A, const VList &F, uint32_t *lds, uint32_t lane) {
+    Res x;
+    x.na = A.n;
+    x.nf = F.n;
+    x.lds = A.n <= kTile && F.n <= kTile;
+    if (!x.lds) {
+        x.as = A.s;
+        x.ae = A.e;
+        x.fs = F.s;
+        x.fe = F.e;
+        return x;
+    }
+    wave_lds_sync();   // the previous pair's searches are done
+    for (uint32_t i = lane; i < A.n; i += 64) {
+        lds[i] = gl(A.s, i);
+        lds[kTile + i] = gl(A.e, i);
+    }
+    for (uint32_t i = lane; i < F.n; i += 64) {
+        lds[2 * kTile + i] = gl(F.s, i);
+        lds[3 * kTile + i] = gl(F.e, i);
+    }
+    wave_lds_sync();
+    x.as = lds;
+    x.ae = lds + kTile;
+    x.fs = lds + 2 * kTile;
+    x.fe = lds + 3 * kTile;
+    return x;
+}
+
 template <uint32_t MODE>
 __global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
+    __shared__ uint32_t lds_all[kWavesPerBlock][4 * kTile];
     const uint32_t lane = threadIdx.x & 63;
+    uint32_t *lds = lds_all[threadIdx.x >> 6];
     const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const uint64_t waves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
@@ -121,30 +210,43 @@ __global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
         if (r >= a.n_r || s >= a.n_s) {
             v = APRIL_BAD_PAIR;
         } else if (MODE == kWithin) {
+            // s resident (its A for AA, its F for containment); A(r) streamed
             const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r);
-            const VList As = list_of(a.offAs, a.sAs, a.eAs, s), Fs = list_of(a.offFs, a.sFs, a.eFs, s);
-            v = !any_overlap(As, Ar, 0, lane) ? APRIL_TN : all_inside(Fs, Ar, lane) ? APRIL_TH : APRIL_INDECISIVE;
+            const Res xs = stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane);
+            v = !any_overlap(xs, false, Ar, 0, lane) ? APRIL_TN
+                : all_inside_f(xs, Ar, lane)          ? APRIL_TH
+                                                      : APRIL_INDECISIVE;
         } else if (MODE == kLinestring) {
-            const VList Ap = list_of(a.offAr, a.sAr, a.eAr, r), Fp = list_of(a.offFr, a.sFr, a.eFr, r);
+            // the linestring's cells searched (in LDS when at most 4 kTile
+            // of them: a linestring has more cells than a polygon has
+            // intervals); the polygon's A- and F-lists streamed
             const VList Cl = list_of(a.offAs, a.sAs, nullptr, s);
-            v = !any_overlap(Ap, Cl, 0, lane) ? APRIL_TN : any_overlap(Fp, Cl, 0, lane) ? APRIL_TH
-                                                                                      : APRIL_INDECISIVE;
-        } else {
-            const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r), Fr = list_of(a.offFr, a.sFr, a.eFr, r);
-            const VList As = list_of(a.offAs, a.sAs, a.eAs, s), Fs = list_of(a.offFs, a.sFs, a.eFs, s);
-            if (a.shift_r == 0 && a.shift_s == 0) {   // one order: Alg. 2 unchanged
-                v = !any_overlap(As, Ar, 0, lane)                                   ? APRIL_TN
-                    : any_overlap(Fs, Ar, 0, lane) || any_overlap(As, Fr, 0, lane) ? APRIL_TH
-                                                                                     : APRIL_INDECISIVE;
-            } else if (a.shift_r) {                   // R finer: stream its mapped A
-                v = !any_overlap(As, Ar, a.shift_r, lane) ? APRIL_TN
-                    : any_overlap(Fs, Ar, a.shift_r, lane) ? APRIL_TH
-                                                           : APRIL_INDECISIVE;
-            } else {                                  // S finer
-                v = !any_overlap(Ar, As, a.shift_s, lane) ? APRIL_TN
-                    : any_overlap(Fr, As, a.shift_s, lane) ? APRIL_TH
-                                                           : APRIL_INDECISIVE;
+            const bool in_lds = Cl.n <= 4 * kTile;
+            if (in_lds) {
+                wave_lds_sync();
+                for (uint32_t i = lane; i < Cl.n; i += 64) lds[i] = gl(Cl.s, i);
+                wave_lds_sync();
             }
+            const uint32_t *c = in_lds ? lds : Cl.s;
+            v = !any_cell_overlap(c, Cl.n, in_lds, list_of(a.offAr, a.sAr, a.eAr, r), lane) ? APRIL_TN
+                : any_cell_overlap(c, Cl.n, in_lds, list_of(a.offFr, a.sFr, a.eFr, r), lane) ? APRIL_TH
+                                                                                             : APRIL_INDECISIVE;
+        } else if (a.shift_r == 0 && a.shift_s == 0) {   // one order: Alg. 2 unchanged
+            const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r), Fr = list_of(a.offFr, a.sFr, a.eFr, r);
+            const Res xs = stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane);
+            v = !any_overlap(xs, false, Ar, 0, lane)                                      ? APRIL_TN
+                : any_overlap(xs, true, Ar, 0, lane) || any_overlap(xs, false, Fr, 0, lane) ? APRIL_TH
+                                                                                          : APRIL_INDECISIVE;
+        } else {
+            // the coarse side resident; the fine side's A streamed, mapped
+            const bool r_fine = a.shift_r != 0;
+            const VList Af = r_fine ? list_of(a.offAr, a.sAr, a.eAr, r) : list_of(a.offAs, a.sAs, a.eAs, s);
+            const Res xc = r_fine ? stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane)
+                                  : stage(list_of(a.offAr, a.sAr, a.eAr, r), list_of(a.offFr, a.sFr, a.eFr, r), lds, lane);
+            const uint32_t sh = r_fine ? a.shift_r : a.shift_s;
+            v = !any_overlap(xc, false, Af, sh, lane) ? APRIL_TN
+                : any_overlap(xc, true, Af, sh, lane)  ? APRIL_TH
+                                                       : APRIL_INDECISIVE;
         }
         if (lane == 0) {
             a.verdict[p] = v;

@@ -51,6 +51,7 @@ extern "C" {
 #define APRIL_E_HIP -4       /* a HIP runtime call failed */
 #define APRIL_E_CORRUPT -5   /* lists not sorted/disjoint (validation) */
 #define APRIL_E_NODEV -6     /* no usable gfx950 device */
+#define APRIL_E_IO -7        /* a file could not be opened, read or written */
 
 /* verdicts (Sec. 4.2) */
 #define APRIL_TN 0
@@ -185,6 +186,30 @@ void april_lists_free(april_lists_t *lists);
  * device (the decoder the filter kernels use).  Synchronous on hip_stream.
  */
 int april_lists_download(const april_lists_t *device_lists, void *hip_stream, april_lists_t **out);
+
+/*
+ * List files: the approximations are precomputed once and stored (Sec. 4.1,
+ * Sec. 6), then reloaded.  A file holds one collection of host lists: a
+ * versioned 88-byte header (magic "APRILLST", version 1, the grid, the
+ * partition key of a partitioned collection, the counts), the six raw arrays
+ * of april_lists_export in that order (little-endian), and a SHA-256
+ * (FIPS 180-4) of every byte before it.  The raw form only: compress at
+ * upload (april_lists_to_device with APRIL_CODEC_VBYTE).
+ *
+ * april_lists_save writes `path` through `path`.tmp and a rename, so a
+ * reader never sees a partial file (two saves to one path at once race).
+ * Host lists only (download device lists first): APRIL_E_INVALID; a file
+ * that cannot be created or written: APRIL_E_IO.
+ *
+ * april_lists_load reads a file into new host lists (free with
+ * april_lists_free).  A missing or unreadable file gives APRIL_E_IO; a file
+ * whose header, size or digest does not match, or whose grid is not exact,
+ * gives APRIL_E_CORRUPT.  With validate != 0 the lists are also checked as
+ * april_lists_from_arrays does (sorted, disjoint, F inside A), else only
+ * the offsets are (enough for every access to stay in bounds).
+ */
+int april_lists_save(const april_lists_t *lists, const char *path);
+int april_lists_load(const char *path, int validate, april_lists_t **out);
 
 /* ---------------------------------------------------------------- filter */
 #define APRIL_SCHED_PLAIN 0u    /* one wavefront per candidate pair */

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libapril.so")
 
 OK, PENDING = 0, 1
-E_INVALID, E_GRID, E_NOMEM, E_HIP, E_CORRUPT, E_NODEV = -1, -2, -3, -4, -5, -6
+E_INVALID, E_GRID, E_NOMEM, E_HIP, E_CORRUPT, E_NODEV, E_IO = -1, -2, -3, -4, -5, -6, -7
 TN, TH, INDECISIVE, BAD_PAIR = 0, 1, 2, 255
 STRICT = 1
 GRID_PARTITIONED = 1
@@ -27,7 +27,8 @@ SCHED_PLAIN, SCHED_BATCHED = 0, 1
 VALIDATE = 1
 
 _ERRNAMES = {E_INVALID: "APRIL_E_INVALID", E_GRID: "APRIL_E_GRID", E_NOMEM: "APRIL_E_NOMEM",
-             E_HIP: "APRIL_E_HIP", E_CORRUPT: "APRIL_E_CORRUPT", E_NODEV: "APRIL_E_NODEV"}
+             E_HIP: "APRIL_E_HIP", E_CORRUPT: "APRIL_E_CORRUPT", E_NODEV: "APRIL_E_NODEV",
+             E_IO: "APRIL_E_IO"}
 
 
 class AprilError(RuntimeError):
@@ -109,6 +110,8 @@ def lib():
     L.april_lists_to_device.argtypes = [P, u32, P, C.POINTER(P)]
     L.april_lists_download.argtypes = [P, P, C.POINTER(P)]
     L.april_lists_free.argtypes = [P]
+    L.april_lists_save.argtypes = [P, C.c_char_p]
+    L.april_lists_load.argtypes = [C.c_char_p, i32, C.POINTER(P)]
     L.april_lists_free.restype = None
     L.april_filter_pairs.argtypes = [P, P, P, P, u64, P, P, C.POINTER(april_filter_opts_t), P]
     L.april_alg2_bytes.argtypes = [P, P, P, P, u64, P, P]
@@ -287,6 +290,19 @@ def april_filter_workspace_size(n_pairs: int, schedule=SCHED_BATCHED) -> int:
     out = C.c_uint64()
     _check(lib().april_filter_workspace_size(n_pairs, C.byref(o), C.byref(out)))
     return out.value
+
+
+def april_lists_save(host: Lists, path) -> None:
+    """Write host lists to a versioned list file sealed with its SHA-256."""
+    _check(lib().april_lists_save(host.handle, os.fsencode(path)))
+
+
+def april_lists_load(path, validate: bool = True) -> Lists:
+    """Host lists read back from a list file (digest checked; with validate,
+    the lists too)."""
+    h = C.c_void_p()
+    _check(lib().april_lists_load(os.fsencode(path), int(validate), C.byref(h)))
+    return Lists(h.value)
 
 
 def april_lists_download(dev: Lists, stream=None) -> Lists:

@@ -112,6 +112,12 @@ void parallel(int threads, F fn) {
     for (auto &t : th) t.join();
 }
 int host_threads();
+
+// Offsets start at 0 and never decrease (APRIL_E_INVALID); with `full`, the
+// lists are sorted, disjoint and every F interval lies inside an A interval
+// (APRIL_E_CORRUPT).  Reads n + 1 offsets and the intervals they span.
+int check_lists(uint64_t n, const uint64_t *off_a, const uint32_t *start_a, const uint32_t *end_a,
+                const uint64_t *off_f, const uint32_t *start_f, const uint32_t *end_f, bool full);
 // april_build_lists with at most max_threads host threads (polygons in
 // parallel, or one large polygon split over them)
 int build_lists_threads(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off, uint64_t n,

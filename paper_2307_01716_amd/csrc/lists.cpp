@@ -140,30 +140,16 @@ uint64_t vbyte_encode(const uint32_t *s, const uint32_t *e, uint64_t n, std::vec
     return out.size() - base;
 }
 
-}  // namespace april
-
-using namespace april;
-
-extern "C" {
-
-const char *april_last_error(void) { return april::g_last_error.c_str(); }
-
-int april_lists_from_arrays(const april_grid_t *grid, uint64_t n, const uint64_t *off_a,
-                            const uint32_t *start_a, const uint32_t *end_a, const uint64_t *off_f,
-                            const uint32_t *start_f, const uint32_t *end_f, int validate,
-                            april_lists_t **out) {
-    clear_error();
-    if (!grid || !out || !off_a || !off_f) return fail(APRIL_E_INVALID, "NULL argument");
-    LatticeGrid lg;
-    if (int rc = lattice_grid(grid, &lg)) return rc;
-    const uint64_t na = off_a[n], nf = off_f[n];
-    if ((na && (!start_a || !end_a)) || (nf && (!start_f || !end_f)))
-        return fail(APRIL_E_INVALID, "NULL interval arrays");
+// Offsets start at 0 and never decrease; with `full`, every list is sorted,
+// disjoint and non-empty per interval, and every F interval lies inside one
+// A interval (a Full cell is a cell of the polygon, Sec. 4.1).
+int check_lists(uint64_t n, const uint64_t *off_a, const uint32_t *start_a, const uint32_t *end_a,
+                const uint64_t *off_f, const uint32_t *start_f, const uint32_t *end_f, bool full) {
     if (off_a[0] != 0 || off_f[0] != 0) return fail(APRIL_E_INVALID, "offsets must start at 0");
     for (uint64_t k = 0; k < n; k++)
         if (off_a[k + 1] < off_a[k] || off_f[k + 1] < off_f[k])
             return fail(APRIL_E_INVALID, "offsets must be non-decreasing");
-    if (validate) {
+    if (full) {
         auto check = [&](const uint64_t *off, const uint32_t *s, const uint32_t *e) -> bool {
             for (uint64_t k = 0; k < n; k++)
                 for (uint64_t t = off[k]; t < off[k + 1]; t++) {
@@ -185,6 +171,29 @@ int april_lists_from_arrays(const april_grid_t *grid, uint64_t n, const uint64_t
             }
         }
     }
+    return APRIL_OK;
+}
+
+}  // namespace april
+
+using namespace april;
+
+extern "C" {
+
+const char *april_last_error(void) { return april::g_last_error.c_str(); }
+
+int april_lists_from_arrays(const april_grid_t *grid, uint64_t n, const uint64_t *off_a,
+                            const uint32_t *start_a, const uint32_t *end_a, const uint64_t *off_f,
+                            const uint32_t *start_f, const uint32_t *end_f, int validate,
+                            april_lists_t **out) {
+    clear_error();
+    if (!grid || !out || !off_a || !off_f) return fail(APRIL_E_INVALID, "NULL argument");
+    LatticeGrid lg;
+    if (int rc = lattice_grid(grid, &lg)) return rc;
+    const uint64_t na = off_a[n], nf = off_f[n];
+    if ((na && (!start_a || !end_a)) || (nf && (!start_f || !end_f)))
+        return fail(APRIL_E_INVALID, "NULL interval arrays");
+    if (int rc = check_lists(n, off_a, start_a, end_a, off_f, start_f, end_f, validate != 0)) return rc;
     auto *L = new (std::nothrow) april_lists;
     if (!L) return fail(APRIL_E_NOMEM, "out of host memory");
     try {

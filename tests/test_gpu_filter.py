@@ -11,7 +11,8 @@ Cases:
     configuration the benchmark times: every verdict checked against
     properties that hold at any size, a random sample checked against the
     oracle one by one;
-  * edge cases: no pairs, out-of-range indices, duplicated pairs.
+  * edge cases: no pairs, out-of-range indices, duplicated pairs;
+  * lists that went through list files (save, load, upload in both codecs).
 """
 
 import sys
@@ -178,6 +179,21 @@ def test_tiny_end_to_end(tiny, sched):
     april.april_alg2_bytes(dR, dS, cuda(r), cuda(s), by)
     torch.cuda.synchronize()
     assert np.array_equal(by.cpu().numpy().astype(np.uint64), b)
+
+
+def test_tiny_from_list_files(tiny, tmp_path):
+    """Lists saved to list files, loaded, uploaded in both codecs: same verdicts."""
+    R, S, g, LR, LS, r, s, v, b = tiny
+    for name, P in (("r", R), ("s", S)):
+        april.april_lists_save(april.april_build_lists(g, P.xy, P.voff, april.STRICT), tmp_path / name)
+    hR, hS = april.april_lists_load(tmp_path / "r"), april.april_lists_load(tmp_path / "s")
+    for codec in (april.CODEC_RAW, april.CODEC_VBYTE):
+        say(f"[tiny] from list files, codec={codec}")
+        dR, dS = april.april_lists_to_device(hR, codec), april.april_lists_to_device(hS, codec)
+        for sched in ("plain", "batched"):
+            got, cnt = gpu_filter(dR, dS, r, s, **SCHEDULES[sched])
+            assert np.array_equal(got, v)
+            assert np.array_equal(cnt, np.bincount(v, minlength=3))
 
 
 def test_tiny_waves_and_duplicates(tiny):

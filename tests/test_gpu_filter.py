@@ -182,7 +182,8 @@ def test_tiny_end_to_end(tiny, sched):
 
 
 def test_tiny_from_list_files(tiny, tmp_path):
-    """Lists saved to list files, loaded, uploaded in both codecs: same verdicts."""
+    """Lists saved to list files, loaded and uploaded in both codecs give the
+    oracle's verdicts."""
     R, S, g, LR, LS, r, s, v, b = tiny
     for name, P in (("r", R), ("s", S)):
         april.april_lists_save(april.april_build_lists(g, P.xy, P.voff, april.STRICT), tmp_path / name)
@@ -190,7 +191,8 @@ def test_tiny_from_list_files(tiny, tmp_path):
     for codec in (april.CODEC_RAW, april.CODEC_VBYTE):
         say(f"[tiny] from list files, codec={codec}")
         dR, dS = april.april_lists_to_device(hR, codec), april.april_lists_to_device(hS, codec)
-        for sched in ("plain", "batched"):
+        # compressed lists run on the batched schedule only
+        for sched in ("plain", "batched") if codec == april.CODEC_RAW else ("batched",):
             got, cnt = gpu_filter(dR, dS, r, s, **SCHEDULES[sched])
             assert np.array_equal(got, v)
             assert np.array_equal(cnt, np.bincount(v, minlength=3))

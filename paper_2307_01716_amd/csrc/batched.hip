@@ -70,6 +70,7 @@ struct BatchArgs {
     uint32_t grab;               // pairs per grab (<= 64)
     uint32_t tail_grab;          // pairs per grab near a range's end
     uint64_t tail_pairs;         // "near the end": fewer pairs than this left
+    uint32_t shift_r, shift_s;   // mixed orders: bits dropped from the finer side's A
 };
 
 // ---------------------------------------------------------------- binning
@@ -187,10 +188,15 @@ __device__ __forceinline__ void load_resident(const Resident &x, const uint32_t 
 // element starts at or after `stop`; true iff some element overlaps it.  With
 // FA, each element that overlaps the A-list is also tested against the
 // resident F-list, and an overlap there sets *th and ends the scan.
-template <int TILE, int C, bool FA>
+//
+// With MIX the streamed list is the finer side's A-list and each element is
+// mapped to the resident (coarser) grid as it is read: [s >> sh,
+// ((e - 1) >> sh) + 1).  Mapped elements stay sorted by start and by end
+// (they may touch or overlap each other), which is all the scan needs.
+template <int TILE, int C, bool FA, bool MIX>
 __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *__restrict__ ys,
                                              const uint32_t *__restrict__ ye, uint32_t j, uint32_t m,
-                                             uint32_t stop, uint32_t lane, bool *th) {
+                                             uint32_t stop, uint32_t lane, bool *th, uint32_t sh) {
     bool any = false;
     for (; j < m; j += 64 * C) {
         uint32_t s[C], e[C];
@@ -200,6 +206,10 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
             const uint32_t k = j + c * 64 + lane;
             s[c] = k < m ? gload(ys, k) : 0u;
             e[c] = k < m ? gload(ye, k) : 0u;
+            if (MIX) {
+                s[c] >>= sh;
+                e[c] = k < m ? ((e[c] - 1) >> sh) + 1 : 0u;
+            }
         }
         // this chunk and all later ones start at or after the piece's end
         if (uniform(s[0]) >= stop) break;
@@ -241,27 +251,33 @@ struct PairLists {
 // Joins of one resident piece (key range [k0, k1)) with the streamed lists:
 // 0 = no AA overlap, 1 = a true hit (FA or AF overlap), 2 = AA overlap only.
 // Every value here is wave-uniform; uniform() says so to the compiler.
-template <int TILE, int C>
+//
+// With MIX, Y is the finer side's A-list mapped to X's grid (shift sh), and
+// only the coarse side's F decides a true hit (Sec. 5.3): no AF pass.
+template <int TILE, int C, bool MIX>
 __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLists &L, uint32_t k0, uint32_t k1,
-                                               uint32_t search_min, uint32_t lane) {
+                                               uint32_t search_min, uint32_t lane, uint32_t sh) {
     // Y elements that can meet this piece: end above x_lo, start below x_hi
     const uint32_t x_lo = max(k0, uniform(res.as[0]));
     const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
     const bool narrow = k0 > 0;
     bool th = false;
-    const uint32_t ja = (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, x_lo, lane)) : 0;
-    if (!stream_piece<TILE, C, true>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th)) return 0;
+    // a mapped end ((e - 1) >> sh) + 1 is above x_lo iff e is above x_lo << sh
+    const uint32_t ja =
+        (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, MIX ? x_lo << sh : x_lo, lane)) : 0;
+    if (!stream_piece<TILE, C, true, MIX>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th, sh)) return 0;
     if (th) return 1;
+    if (MIX) return 2;
     const uint32_t jf = (narrow || L.nyf > search_min) ? uniform(wave_first_above(L.yfe, L.nyf, x_lo, lane)) : 0;
-    return stream_piece<TILE, C, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th) ? 1 : 2;
+    return stream_piece<TILE, C, false, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th, 0) ? 1 : 2;
 }
 
 // Alg. 2's verdict for one pair, by the whole wave.  When both of X's lists
 // are shorter than TILE they are one piece, kept resident for the next pair
 // with the same `key`; otherwise X is loaded piece by piece.
-template <int TILE, int C>
+template <int TILE, int C, bool MIX>
 __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, const PairLists &L,
-                              uint32_t search_min, uint32_t lane) {
+                              uint32_t search_min, uint32_t lane, uint32_t sh) {
     if (L.nxa == 0 || L.nya == 0) return APRIL_TN;
     if (L.nxa < TILE && L.nxf < TILE) {
         if (key != cached) {
@@ -272,7 +288,7 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
             res.nf = L.nxf;
             cached = key;
         }
-        const uint32_t j = join_piece<TILE, C>(res, L, 0, kNone, search_min, lane);
+        const uint32_t j = join_piece<TILE, C, MIX>(res, L, 0, kNone, search_min, lane, sh);
         return j == 0 ? APRIL_TN : j == 1 ? APRIL_TH : APRIL_INDECISIVE;
     }
     cached = kNone;
@@ -297,7 +313,7 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
         wave_lds_sync();
         res.na = a1 - a0;
         res.nf = f1 - f0;
-        const uint32_t j = join_piece<TILE, C>(res, L, k0, k1, search_min, lane);
+        const uint32_t j = join_piece<TILE, C, MIX>(res, L, k0, k1, search_min, lane, sh);
         if (j == 1) return APRIL_TH;
         aa |= j == 2;
         if (k1 == kNone) break;
@@ -347,7 +363,7 @@ __device__ __forceinline__ PairLists lane_pair(const PairLists &m, uint32_t k) {
     return L;
 }
 
-template <int TILE, int C>
+template <int TILE, int C, bool MIX>
 // Register budget: 8 waves per SIMD where LDS allows it (TILE <= 256).
 // The hardware allocates SGPRs in blocks of 16, and above 80 SGPRs fewer
 // waves fit than the compiler's occupancy estimate says: the kernel at 97
@@ -415,8 +431,10 @@ void k_batched(BatchArgs b) {
                     const uint32_t mr = max(nar, nfr), ms = max(nas, nfs);
                     // R resident when its lists fit a tile; else S when its
                     // do or when neither does and S's are shorter
-                    const bool xs = !(mr < TILE) && (ms < TILE || ms < mr);
-                    if (max(mr, ms) <= pb->thread_max) seq = true;
+                    // (mixed orders: the coarser side, whose lists stay
+                    // sorted and disjoint; every pair by the wave)
+                    const bool xs = MIX ? pb->shift_r != 0 : !(mr < TILE) && (ms < TILE || ms < mr);
+                    if (!MIX && max(mr, ms) <= pb->thread_max) seq = true;
                     else wave = true;
                     m = pair_lists(a, xs, ar0, nar, fr0, nfr, as0, nas, fs0, nfs);
                     key = (xs ? s : r) | (xs ? kSideS : 0u);
@@ -429,7 +447,9 @@ void k_batched(BatchArgs b) {
                 const uint32_t k2 = uint32_t(__builtin_ctzll(todo));
                 todo &= todo - 1;
                 const PairLists L = lane_pair(m, k2);
-                const uint32_t v = wave_pair<TILE, C>(res, cached, lane_val(key, k2), L, search_min, lane);
+                const uint32_t kk = lane_val(key, k2);
+                const uint32_t sh = MIX ? ((kk & kSideS) ? pb->shift_r : pb->shift_s) : 0;
+                const uint32_t v = wave_pair<TILE, C, MIX>(res, cached, kk, L, search_min, lane, sh);
                 vv = lane == k2 ? v : vv;
             }
             // very short lists: every such lane runs Alg. 2 on its own pair
@@ -468,12 +488,12 @@ void k_batched(BatchArgs b) {
 }
 
 
-template <int TILE, int C>
+template <int TILE, int C, bool MIX = false>
 int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     static int per_cu = 0;   // resident workgroups per CU (same on every gfx950 device)
     if (!per_cu) {
         int q = 0;
-        APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_batched<TILE, C>, kBlock, 0));
+        APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_batched<TILE, C, MIX>, kBlock, 0));
         per_cu = q < 1 ? 1 : q;
     }
     // default residency (measured on the at-scale join): 4 waves per SIMD
@@ -484,7 +504,7 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     // a range is near its end once its waves have about two full grabs each left
     BatchArgs bb = b;
     bb.tail_pairs = 2ull * b.grab * kWavesPerBlock * ((blocks + b.xcds - 1) / b.xcds);
-    k_batched<TILE, C><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
+    k_batched<TILE, C, MIX><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
     APRIL_HIP_TRY(hipGetLastError());
     if (b.f.counts) {
         k_sum_totals<<<1, 64, 0, stream>>>(b.xhead, b.f.counts, 3);
@@ -544,6 +564,7 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     // 64 the at-scale join ran 4% slower (2.13 vs 2.05 ms), with 16 no faster.
     b.grab = 32;
     b.tail_grab = 8;
+    b.shift_r = b.shift_s = 0;
     if (b.thread_max >= tile) return fail(APRIL_E_INVALID, "thread_max must be below tile");
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
@@ -553,6 +574,24 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
         case 512: return launch_t<512>(b, chunk, cus, o.waves, stream);
     }
     return fail(APRIL_E_INVALID, "tile must be 128, 256 or 512");
+}
+
+int launch_batched_mixed(const FilterArgs &a, uint32_t shift_r, uint32_t shift_s, int cus, void *workspace,
+                         hipStream_t stream) {
+    if ((shift_r == 0) == (shift_s == 0)) return fail(APRIL_E_INVALID, "exactly one side must be finer");
+    BatchArgs b;
+    b.f = a;
+    b.xhead = static_cast<unsigned int *>(workspace);
+    b.xcds = uint32_t(xcd_count(cus));
+    b.thread_max = 0;   // unused: every pair by the wave
+    b.search_min = 512;
+    b.grab = 32;
+    b.tail_grab = 8;
+    b.shift_r = shift_r;
+    b.shift_s = shift_s;
+    k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
+    APRIL_HIP_TRY(hipGetLastError());
+    return launch_tc<256, 2, true>(b, cus, 0, stream);
 }
 
 }  // namespace april

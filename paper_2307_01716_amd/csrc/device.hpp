@@ -106,5 +106,14 @@ uint64_t batched_workspace_bytes(uint64_t n_pairs);
 int xcd_count(int cus);
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
                    hipStream_t stream);
+// Kernel arguments of a filter call on device lists R and S (raw codec).
+FilterArgs make_args(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
+                     uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts);
+// The batched schedule for lists on two orders of one data space (Sec. 5.3):
+// exactly one of shift_r, shift_s is non-zero (2 * the order difference);
+// the coarser side is kept resident and the finer side's A-list is mapped
+// to its grid while streamed; true hits come from the coarser side's F only.
+int launch_batched_mixed(const FilterArgs &a, uint32_t shift_r, uint32_t shift_s, int cus, void *workspace,
+                         hipStream_t stream);
 
 }  // namespace april

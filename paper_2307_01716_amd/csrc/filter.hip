@@ -229,9 +229,9 @@ static int check_lists(const april_lists_t *R, const april_lists_t *S) {
     return APRIL_OK;
 }
 
-static FilterArgs make_args(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
-                            const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
-                            unsigned long long *counts) {
+namespace april {
+FilterArgs make_args(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
+                     uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts) {
     FilterArgs a;
     a.Ar = {R->d.off_a, R->d.start_a, R->d.end_a};
     a.Fr = {R->d.off_f, R->d.start_f, R->d.end_f};
@@ -246,6 +246,7 @@ static FilterArgs make_args(const april_lists_t *R, const april_lists_t *S, cons
     a.counts = counts;
     return a;
 }
+}  // namespace april
 
 extern "C" int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
                                 const uint32_t *d_s, uint64_t n_pairs, uint64_t *d_bytes,

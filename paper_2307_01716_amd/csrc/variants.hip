@@ -4,9 +4,9 @@
 //   polygon-linestring joins (Sec. 4.3.3): A(p) and F(p) against the
 //     linestring's cell ids taken as intervals [c, c+1) (here the cells are
 //     searched and the polygon's lists streamed);
-//   different granularity (Sec. 5.3): the finer side's A-intervals mapped to
-//     the coarser grid, a' = [a_s >> n, ((a_e - 1) >> n) + 1) (the paper's
-//     inclusive end in half-open form), then AA and the coarse side's F only.
+//   different granularity (Sec. 5.3): on the batched schedule of the
+//     filter (the coarser side resident, the finer side's A mapped while
+//     streamed), launched from here.
 //
 // One wave per pair, pairs dealt to waves in order (wave w takes pairs
 // w, w + W, ...).  One object's A- and F-lists are made searchable (copied
@@ -16,9 +16,7 @@
 // after its element starts: its element overlaps the list iff that interval
 // starts before the element ends, and lies inside it iff that interval also
 // starts at or before the element and ends at or after it.  A ballot per
-// step ends a join on its first decisive element.  Streaming the mapped side
-// of a mixed-order pair keeps the searched side sorted and disjoint (mapped
-// intervals may touch or overlap each other).
+// step ends a join on its first decisive element.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,20 +33,19 @@ struct VList {
     uint32_t n;
 };
 
-enum Mode : uint32_t { kWithin = 0, kLinestring = 1, kMixed = 2 };
+enum Mode : uint32_t { kWithin = 0, kLinestring = 1 };
 
 struct VArgs {
-    // R side (within: r; linestring: polygons; mixed: R)
+    // R side (within: r; linestring: polygons)
     const uint64_t *offAr, *offFr;
     const uint32_t *sAr, *eAr, *sFr, *eFr;
-    // S side (within: s; linestring: the cells; mixed: S)
+    // S side (within: s; linestring: the cells)
     const uint64_t *offAs, *offFs;
     const uint32_t *sAs, *eAs, *sFs, *eFs;
     const uint32_t *r, *s;
     uint64_t n_pairs, n_r, n_s;
     uint8_t *verdict;
     unsigned int *ctr;   // count slots (totals), or nullptr
-    uint32_t shift_r, shift_s;   // mixed: bits to drop from R's / S's A-intervals (one of them is 0)
 };
 
 __device__ __forceinline__ uint32_t gl(const uint32_t *p, uint64_t i) {
@@ -77,10 +74,9 @@ __device__ __forceinline__ uint32_t first_ending_after(const uint32_t *e, uint32
     return lo;
 }
 
-__device__ __forceinline__ void element(const VList &Y, uint32_t j, uint32_t shift, uint32_t &y0, uint32_t &y1) {
-    const uint32_t s = gl(Y.s, j), e = Y.e ? gl(Y.e, j) : s + 1;
-    y0 = s >> shift;
-    y1 = ((e - 1) >> shift) + 1;
+__device__ __forceinline__ void element(const VList &Y, uint32_t j, uint32_t &y0, uint32_t &y1) {
+    y0 = gl(Y.s, j);
+    y1 = Y.e ? gl(Y.e, j) : y0 + 1;
 }
 
 template <bool LDS>
@@ -96,9 +92,9 @@ __device__ __forceinline__ bool inside(const uint32_t *xs, const uint32_t *xe, u
     return i < n && (LDS ? xs[i] : gl(xs, i)) <= y0 && y1 <= (LDS ? xe[i] : gl(xe, i));
 }
 
-// Does any element of Y (mapped by `shift`) overlap the resident A (f =
-// false) or F list?  Whole wave.
-__device__ bool any_overlap(const Res &x, bool f, const VList &Y, uint32_t shift, uint32_t lane) {
+// Does any element of Y overlap the resident A (f = false) or F list?
+// Whole wave.
+__device__ bool any_overlap(const Res &x, bool f, const VList &Y, uint32_t lane) {
     const uint32_t *xs = f ? x.fs : x.as, *xe = f ? x.fe : x.ae;
     const uint32_t n = f ? x.nf : x.na;
     if (n == 0) return false;
@@ -107,7 +103,7 @@ __device__ bool any_overlap(const Res &x, bool f, const VList &Y, uint32_t shift
         bool h = false;
         if (j < Y.n) {
             uint32_t y0, y1;
-            element(Y, j, shift, y0, y1);
+            element(Y, j, y0, y1);
             h = x.lds ? overlaps<true>(xs, xe, n, y0, y1) : overlaps<false>(xs, xe, n, y0, y1);
         }
         if (__any(h)) return true;
@@ -122,7 +118,7 @@ __device__ bool all_inside_f(const Res &x, const VList &Y, uint32_t lane) {
         bool miss = false;
         if (j < Y.n) {
             uint32_t y0, y1;
-            element(Y, j, 0, y0, y1);
+            element(Y, j, y0, y1);
             miss = !(x.lds ? inside<true>(x.fs, x.fe, x.nf, y0, y1) : inside<false>(x.fs, x.fe, x.nf, y0, y1));
         }
         if (__any(miss)) return false;
@@ -213,9 +209,9 @@ __global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
             // s resident (its A for AA, its F for containment); A(r) streamed
             const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r);
             const Res xs = stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane);
-            v = !any_overlap(xs, false, Ar, 0, lane) ? APRIL_TN
-                : all_inside_f(xs, Ar, lane)          ? APRIL_TH
-                                                      : APRIL_INDECISIVE;
+            v = !any_overlap(xs, false, Ar, lane) ? APRIL_TN
+                : all_inside_f(xs, Ar, lane)       ? APRIL_TH
+                                                   : APRIL_INDECISIVE;
         } else if (MODE == kLinestring) {
             // the linestring's cells searched (in LDS when at most 4 kTile
             // of them: a linestring has more cells than a polygon has
@@ -231,22 +227,6 @@ __global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
             v = !any_cell_overlap(c, Cl.n, in_lds, list_of(a.offAr, a.sAr, a.eAr, r), lane) ? APRIL_TN
                 : any_cell_overlap(c, Cl.n, in_lds, list_of(a.offFr, a.sFr, a.eFr, r), lane) ? APRIL_TH
                                                                                              : APRIL_INDECISIVE;
-        } else if (a.shift_r == 0 && a.shift_s == 0) {   // one order: Alg. 2 unchanged
-            const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r), Fr = list_of(a.offFr, a.sFr, a.eFr, r);
-            const Res xs = stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane);
-            v = !any_overlap(xs, false, Ar, 0, lane)                                      ? APRIL_TN
-                : any_overlap(xs, true, Ar, 0, lane) || any_overlap(xs, false, Fr, 0, lane) ? APRIL_TH
-                                                                                          : APRIL_INDECISIVE;
-        } else {
-            // the coarse side resident; the fine side's A streamed, mapped
-            const bool r_fine = a.shift_r != 0;
-            const VList Af = r_fine ? list_of(a.offAr, a.sAr, a.eAr, r) : list_of(a.offAs, a.sAs, a.eAs, s);
-            const Res xc = r_fine ? stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane)
-                                  : stage(list_of(a.offAr, a.sAr, a.eAr, r), list_of(a.offFr, a.sFr, a.eFr, r), lds, lane);
-            const uint32_t sh = r_fine ? a.shift_r : a.shift_s;
-            v = !any_overlap(xc, false, Af, sh, lane) ? APRIL_TN
-                : any_overlap(xc, true, Af, sh, lane)  ? APRIL_TH
-                                                       : APRIL_INDECISIVE;
         }
         if (lane == 0) {
             a.verdict[p] = v;
@@ -279,8 +259,7 @@ int launch_variant(uint32_t mode, VArgs a, unsigned long long *counts, hipStream
         const uint32_t blocks = uint32_t((waves + kWavesPerBlock - 1) / kWavesPerBlock);
         switch (mode) {
             case kWithin: k_variant<kWithin><<<blocks, kBlock, 0, stream>>>(a); break;
-            case kLinestring: k_variant<kLinestring><<<blocks, kBlock, 0, stream>>>(a); break;
-            default: k_variant<kMixed><<<blocks, kBlock, 0, stream>>>(a); break;
+            default: k_variant<kLinestring><<<blocks, kBlock, 0, stream>>>(a); break;
         }
         e = hipGetLastError();
     }
@@ -380,10 +359,25 @@ extern "C" int april_filter_mixed(const april_lists_t *R, const april_lists_t *S
         S->partition_key)
         return fail(APRIL_E_GRID, "R and S must cover one data space (same origin and side)");
     if (n_pairs && (!d_r || !d_s || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
-    VArgs a = base_args(R, d_r, d_s, n_pairs, d_verdict);
-    set_s(a, S);
-    a.shift_r = g.order > h.order ? 2 * (g.order - h.order) : 0;
-    a.shift_s = h.order > g.order ? 2 * (h.order - g.order) : 0;
-    return launch_variant(kMixed, a, reinterpret_cast<unsigned long long *>(d_counts),
-                          static_cast<hipStream_t>(hip_stream));
+    const uint32_t shift_r = g.order > h.order ? 2 * (g.order - h.order) : 0;
+    const uint32_t shift_s = h.order > g.order ? 2 * (h.order - g.order) : 0;
+    if (shift_r == 0 && shift_s == 0) {   // one order: Alg. 2 itself
+        april_filter_opts_t o{};
+        o.schedule = APRIL_SCHED_BATCHED;
+        return april_filter_pairs(R, S, d_r, d_s, n_pairs, d_verdict, d_counts, &o, hip_stream);
+    }
+    if (n_pairs >= (1ull << 32)) return fail(APRIL_E_INVALID, "fewer than 2^32 pairs per call");
+    DeviceState *st = nullptr;
+    if (int rc = device_state(&st)) return rc;
+    int cur = 0;
+    APRIL_HIP_TRY(hipGetDevice(&cur));
+    if (cur != R->device) return fail(APRIL_E_INVALID, "current device does not hold the lists");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const FilterArgs fa = make_args(R, S, d_r, d_s, n_pairs, d_verdict, reinterpret_cast<unsigned long long *>(d_counts));
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, batched_workspace_bytes(n_pairs), stream);
+    if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    const int rc = launch_batched_mixed(fa, shift_r, shift_s, st->cus, ws, stream);
+    APRIL_HIP_TRY(hipFreeAsync(ws, stream));
+    return rc;
 }

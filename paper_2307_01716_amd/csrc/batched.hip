@@ -58,6 +58,10 @@
 namespace april {
 namespace {
 
+// Join modes of the kernel: Alg. 2 on one grid; Alg. 2 across two orders
+// (Sec. 5.3); within joins (Sec. 4.3.2).
+constexpr int kAlg2 = 0, kMixedOrders = 1, kWithinJoin = 2;
+
 constexpr uint32_t kSideS = 0x80000000u;   // resident-object key: the object is from S
 constexpr uint32_t kNone = 0xffffffffu;    // no resident object / no upper key bound
 
@@ -241,6 +245,36 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
     return any;
 }
 
+// Does every element of Y[j..m) that starts below `stop` lie inside one
+// resident F interval?  The first F interval ending after the element's
+// start is the only candidate (F is sorted and disjoint); a ballot of misses
+// ends the scan.
+template <int TILE, int C>
+__device__ __forceinline__ bool stream_inside(const Resident &x, const uint32_t *__restrict__ ys,
+                                              const uint32_t *__restrict__ ye, uint32_t j, uint32_t m,
+                                              uint32_t stop, uint32_t lane) {
+    for (; j < m; j += 64 * C) {
+        uint32_t s[C], e[C];
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            const uint32_t k = j + c * 64 + lane;
+            s[c] = k < m ? gload(ys, k) : stop;   // lanes past the end take no part
+            e[c] = k < m ? gload(ye, k) : 0u;
+        }
+        if (uniform(s[0]) >= stop) break;
+        bool miss = false;
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            if (s[c] < stop) {
+                const uint32_t *p = lds_first_above<TILE>(x.fe, s[c]);
+                miss |= !(p[TILE] <= s[c] && e[c] <= p[0]);
+            }
+        }
+        if (__any(miss)) return false;
+    }
+    return true;
+}
+
 // One pair's lists as the wave sees them: X resident, Y streamed.
 struct PairLists {
     const uint32_t *xas, *xae, *xfs, *xfe;
@@ -252,11 +286,16 @@ struct PairLists {
 // 0 = no AA overlap, 1 = a true hit (FA or AF overlap), 2 = AA overlap only.
 // Every value here is wave-uniform; uniform() says so to the compiler.
 //
-// With MIX, Y is the finer side's A-list mapped to X's grid (shift sh), and
-// only the coarse side's F decides a true hit (Sec. 5.3): no AF pass.
-template <int TILE, int C, bool MIX>
+// kMixedOrders: Y is the finer side's A-list mapped to X's grid (shift sh),
+// and only the coarse side's F decides a true hit (Sec. 5.3): no AF pass.
+// kWithinJoin: X is s, Y is A(r); bit 0 of the result is an AA overlap in
+// this piece, bit 1 that every element of A(r) meeting [k0, k1) lies inside
+// one F(s) interval; `want` says which of the two to find (a piece answers
+// 0 for a test it skips).
+template <int TILE, int C, int MODE>
 __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLists &L, uint32_t k0, uint32_t k1,
-                                               uint32_t search_min, uint32_t lane, uint32_t sh) {
+                                               uint32_t search_min, uint32_t lane, uint32_t sh, uint32_t want) {
+    constexpr bool MIX = MODE == kMixedOrders;
     // Y elements that can meet this piece: end above x_lo, start below x_hi
     const uint32_t x_lo = max(k0, uniform(res.as[0]));
     const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
@@ -265,6 +304,19 @@ __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLi
     // a mapped end ((e - 1) >> sh) + 1 is above x_lo iff e is above x_lo << sh
     const uint32_t ja =
         (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, MIX ? x_lo << sh : x_lo, lane)) : 0;
+    if (MODE == kWithinJoin) {
+        const bool aa = (want & 1) && stream_piece<TILE, C, false, false>(res, L.yas, L.yae, ja, L.nya, x_hi, lane,
+                                                                          &th, 0);
+        if ((want & 1) && !aa && !narrow && k1 == kNone) return 0;   // one piece and no overlap
+        bool in = false;
+        if (want & 2) {
+            // every element meeting [k0, k1), not only the resident window:
+            // one outside X's intervals is not inside F(s)
+            const uint32_t jc = (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, k0, lane)) : 0;
+            in = stream_inside<TILE, C>(res, L.yas, L.yae, jc, L.nya, k1, lane);
+        }
+        return (aa ? 1u : 0u) | (in ? 2u : 0u);
+    }
     if (!stream_piece<TILE, C, true, MIX>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th, sh)) return 0;
     if (th) return 1;
     if (MIX) return 2;
@@ -275,7 +327,7 @@ __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLi
 // Alg. 2's verdict for one pair, by the whole wave.  When both of X's lists
 // are shorter than TILE they are one piece, kept resident for the next pair
 // with the same `key`; otherwise X is loaded piece by piece.
-template <int TILE, int C, bool MIX>
+template <int TILE, int C, int MODE>
 __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, const PairLists &L,
                               uint32_t search_min, uint32_t lane, uint32_t sh) {
     if (L.nxa == 0 || L.nya == 0) return APRIL_TN;
@@ -288,11 +340,12 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
             res.nf = L.nxf;
             cached = key;
         }
-        const uint32_t j = join_piece<TILE, C, MIX>(res, L, 0, kNone, search_min, lane, sh);
+        const uint32_t j = join_piece<TILE, C, MODE>(res, L, 0, kNone, search_min, lane, sh, 3);
+        if (MODE == kWithinJoin) return !(j & 1) ? APRIL_TN : (j & 2) ? APRIL_TH : APRIL_INDECISIVE;
         return j == 0 ? APRIL_TN : j == 1 ? APRIL_TH : APRIL_INDECISIVE;
     }
     cached = kNone;
-    bool aa = false;
+    bool aa = false, in = true;   // (within joins: every piece so far has A(r) inside F(s))
     uint32_t a0 = 0, f0 = 0, k0 = 0;
     for (;;) {
         // at most TILE - 1 A elements from a0; the range ends where the next
@@ -313,15 +366,24 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
         wave_lds_sync();
         res.na = a1 - a0;
         res.nf = f1 - f0;
-        const uint32_t j = join_piece<TILE, C, MIX>(res, L, k0, k1, search_min, lane, sh);
-        if (j == 1) return APRIL_TH;
-        aa |= j == 2;
+        if (MODE == kWithinJoin) {
+            const uint32_t j =
+                join_piece<TILE, C, MODE>(res, L, k0, k1, search_min, lane, sh, (aa ? 0u : 1u) | (in ? 2u : 0u));
+            aa |= (j & 1) != 0;
+            in = in && (j & 2);
+            if (aa && !in) return APRIL_INDECISIVE;
+        } else {
+            const uint32_t j = join_piece<TILE, C, MODE>(res, L, k0, k1, search_min, lane, sh, 3);
+            if (j == 1) return APRIL_TH;
+            aa |= j == 2;
+        }
         if (k1 == kNone) break;
         // next piece: the first elements that end above k1
         k0 = k1;
         a0 = uniform(gload(L.xae, a1 - 1)) > k1 ? a1 - 1 : a1;
         f0 = (f1 > 0 && uniform(gload(L.xfe, f1 - 1)) > k1) ? f1 - 1 : f1;
     }
+    if (MODE == kWithinJoin) return !aa ? APRIL_TN : in ? APRIL_TH : APRIL_INDECISIVE;
     return aa ? APRIL_INDECISIVE : APRIL_TN;
 }
 
@@ -363,7 +425,7 @@ __device__ __forceinline__ PairLists lane_pair(const PairLists &m, uint32_t k) {
     return L;
 }
 
-template <int TILE, int C, bool MIX>
+template <int TILE, int C, int MODE>
 // Register budget: 8 waves per SIMD where LDS allows it (TILE <= 256).
 // The hardware allocates SGPRs in blocks of 16, and above 80 SGPRs fewer
 // waves fit than the compiler's occupancy estimate says: the kernel at 97
@@ -432,9 +494,11 @@ void k_batched(BatchArgs b) {
                     // R resident when its lists fit a tile; else S when its
                     // do or when neither does and S's are shorter
                     // (mixed orders: the coarser side, whose lists stay
-                    // sorted and disjoint; every pair by the wave)
-                    const bool xs = MIX ? pb->shift_r != 0 : !(mr < TILE) && (ms < TILE || ms < mr);
-                    if (!MIX && max(mr, ms) <= pb->thread_max) seq = true;
+                    // sorted and disjoint; within joins: s, the container)
+                    const bool xs = MODE == kMixedOrders ? pb->shift_r != 0
+                                    : MODE == kWithinJoin ? true
+                                                          : !(mr < TILE) && (ms < TILE || ms < mr);
+                    if (MODE == kAlg2 && max(mr, ms) <= pb->thread_max) seq = true;
                     else wave = true;
                     m = pair_lists(a, xs, ar0, nar, fr0, nfr, as0, nas, fs0, nfs);
                     key = (xs ? s : r) | (xs ? kSideS : 0u);
@@ -448,8 +512,8 @@ void k_batched(BatchArgs b) {
                 todo &= todo - 1;
                 const PairLists L = lane_pair(m, k2);
                 const uint32_t kk = lane_val(key, k2);
-                const uint32_t sh = MIX ? ((kk & kSideS) ? pb->shift_r : pb->shift_s) : 0;
-                const uint32_t v = wave_pair<TILE, C, MIX>(res, cached, kk, L, search_min, lane, sh);
+                const uint32_t sh = MODE == kMixedOrders ? ((kk & kSideS) ? pb->shift_r : pb->shift_s) : 0;
+                const uint32_t v = wave_pair<TILE, C, MODE>(res, cached, kk, L, search_min, lane, sh);
                 vv = lane == k2 ? v : vv;
             }
             // very short lists: every such lane runs Alg. 2 on its own pair
@@ -488,12 +552,12 @@ void k_batched(BatchArgs b) {
 }
 
 
-template <int TILE, int C, bool MIX = false>
+template <int TILE, int C, int MODE = kAlg2>
 int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     static int per_cu = 0;   // resident workgroups per CU (same on every gfx950 device)
     if (!per_cu) {
         int q = 0;
-        APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_batched<TILE, C, MIX>, kBlock, 0));
+        APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_batched<TILE, C, MODE>, kBlock, 0));
         per_cu = q < 1 ? 1 : q;
     }
     // default residency (measured on the at-scale join): 4 waves per SIMD
@@ -504,7 +568,7 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     // a range is near its end once its waves have about two full grabs each left
     BatchArgs bb = b;
     bb.tail_pairs = 2ull * b.grab * kWavesPerBlock * ((blocks + b.xcds - 1) / b.xcds);
-    k_batched<TILE, C, MIX><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
+    k_batched<TILE, C, MODE><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
     APRIL_HIP_TRY(hipGetLastError());
     if (b.f.counts) {
         k_sum_totals<<<1, 64, 0, stream>>>(b.xhead, b.f.counts, 3);
@@ -591,7 +655,22 @@ int launch_batched_mixed(const FilterArgs &a, uint32_t shift_r, uint32_t shift_s
     b.shift_s = shift_s;
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
-    return launch_tc<256, 2, true>(b, cus, 0, stream);
+    return launch_tc<256, 2, kMixedOrders>(b, cus, 0, stream);
+}
+
+int launch_batched_within(const FilterArgs &a, int cus, void *workspace, hipStream_t stream) {
+    BatchArgs b;
+    b.f = a;
+    b.xhead = static_cast<unsigned int *>(workspace);
+    b.xcds = uint32_t(xcd_count(cus));
+    b.thread_max = 0;   // unused: every pair by the wave
+    b.search_min = 512;
+    b.grab = 32;
+    b.tail_grab = 8;
+    b.shift_r = b.shift_s = 0;
+    k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
+    APRIL_HIP_TRY(hipGetLastError());
+    return launch_tc<256, 2, kWithinJoin>(b, cus, 0, stream);
 }
 
 }  // namespace april

@@ -115,5 +115,8 @@ FilterArgs make_args(const april_lists_t *R, const april_lists_t *S, const uint3
 // to its grid while streamed; true hits come from the coarser side's F only.
 int launch_batched_mixed(const FilterArgs &a, uint32_t shift_r, uint32_t shift_s, int cus, void *workspace,
                          hipStream_t stream);
+// The batched schedule for within joins (Sec. 4.3.2): s resident, A(r)
+// streamed for AA, then tested for lying inside F(s).
+int launch_batched_within(const FilterArgs &a, int cus, void *workspace, hipStream_t stream);
 
 }  // namespace april

@@ -1,22 +1,20 @@
-// The filter's query variants on the GPU:
-//   within joins (Sec. 4.3.2): AA, then "every A(r) interval inside one
-//     F(s) interval" -> r within s;
-//   polygon-linestring joins (Sec. 4.3.3): A(p) and F(p) against the
-//     linestring's cell ids taken as intervals [c, c+1) (here the cells are
-//     searched and the polygon's lists streamed);
-//   different granularity (Sec. 5.3): on the batched schedule of the
-//     filter (the coarser side resident, the finer side's A mapped while
-//     streamed), launched from here.
+// The filter's query variants on the GPU.
 //
-// One wave per pair, pairs dealt to waves in order (wave w takes pairs
-// w, w + W, ...).  One object's A- and F-lists are made searchable (copied
-// into the wave's LDS when both hold at most 256 intervals, else read from
-// global memory); the other object's list is streamed, 64 elements per step,
-// one per lane, and each lane binary-searches for the first interval ending
-// after its element starts: its element overlaps the list iff that interval
-// starts before the element ends, and lies inside it iff that interval also
-// starts at or before the element and ends at or after it.  A ballot per
-// step ends a join on its first decisive element.
+// Within joins (Sec. 4.3.2: AA, then every A(r) interval inside one F(s)
+// interval) and different granularity (Sec. 5.3: the finer side's A mapped
+// to the coarser grid, a' = [a_s >> n, ((a_e - 1) >> n) + 1), then AA and the
+// coarser side's F only) run on the filter's batched kernel; their entry
+// points are here.
+//
+// Polygon-linestring joins (Sec. 4.3.3: A(p) and F(p) against the
+// linestring's cell ids taken as intervals [c, c+1)) run on k_linestrings:
+// one wave per pair, pairs dealt to waves in order (wave w takes pairs w,
+// w + W, ...).  The linestring's cells are copied into the wave's LDS when
+// there are at most 1,024 of them (else read from global memory), the
+// polygon's A- and then F-list is streamed, 64 elements per step, one per
+// lane, and each lane binary-searches the cells for the first one at or after
+// its element's start: the element meets a cell iff that cell is below its
+// end.  A ballot per step ends a join on its first hit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,15 +31,13 @@ struct VList {
     uint32_t n;
 };
 
-enum Mode : uint32_t { kWithin = 0, kLinestring = 1 };
-
 struct VArgs {
-    // R side (within: r; linestring: polygons)
+    // the polygons' lists
     const uint64_t *offAr, *offFr;
     const uint32_t *sAr, *eAr, *sFr, *eFr;
-    // S side (within: s; linestring: the cells)
-    const uint64_t *offAs, *offFs;
-    const uint32_t *sAs, *eAs, *sFs, *eFs;
+    // the linestrings' cell ids
+    const uint64_t *offAs;
+    const uint32_t *sAs;
     const uint32_t *r, *s;
     uint64_t n_pairs, n_r, n_s;
     uint8_t *verdict;
@@ -52,83 +48,12 @@ __device__ __forceinline__ uint32_t gl(const uint32_t *p, uint64_t i) {
     return ((const uint32_t __attribute__((address_space(1))) *)p)[i];
 }
 
-// The searched object's lists, in LDS when both fit a tile of kTile
-// intervals (one load round per pair), else read from global memory.
+// Cells kept in a wave's LDS (at most 4 * kTile ids).
 constexpr uint32_t kTile = 256;
-
-struct Res {
-    const uint32_t *as, *ae, *fs, *fe;   // LDS copies (lds) or global lists
-    uint32_t na, nf;
-    bool lds;
-};
-
-// first interval with end > y0 among n sorted, disjoint intervals (ends e)
-template <bool LDS>
-__device__ __forceinline__ uint32_t first_ending_after(const uint32_t *e, uint32_t n, uint32_t y0) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if ((LDS ? e[mid] : gl(e, mid)) <= y0) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ void element(const VList &Y, uint32_t j, uint32_t &y0, uint32_t &y1) {
-    y0 = gl(Y.s, j);
-    y1 = Y.e ? gl(Y.e, j) : y0 + 1;
-}
-
-template <bool LDS>
-__device__ __forceinline__ bool overlaps(const uint32_t *xs, const uint32_t *xe, uint32_t n, uint32_t y0,
-                                         uint32_t y1) {
-    const uint32_t i = first_ending_after<LDS>(xe, n, y0);
-    return i < n && (LDS ? xs[i] : gl(xs, i)) < y1;
-}
-
-template <bool LDS>
-__device__ __forceinline__ bool inside(const uint32_t *xs, const uint32_t *xe, uint32_t n, uint32_t y0, uint32_t y1) {
-    const uint32_t i = first_ending_after<LDS>(xe, n, y0);
-    return i < n && (LDS ? xs[i] : gl(xs, i)) <= y0 && y1 <= (LDS ? xe[i] : gl(xe, i));
-}
-
-// Does any element of Y overlap the resident A (f = false) or F list?
-// Whole wave.
-__device__ bool any_overlap(const Res &x, bool f, const VList &Y, uint32_t lane) {
-    const uint32_t *xs = f ? x.fs : x.as, *xe = f ? x.fe : x.ae;
-    const uint32_t n = f ? x.nf : x.na;
-    if (n == 0) return false;
-    for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
-        const uint32_t j = j0 + lane;
-        bool h = false;
-        if (j < Y.n) {
-            uint32_t y0, y1;
-            element(Y, j, y0, y1);
-            h = x.lds ? overlaps<true>(xs, xe, n, y0, y1) : overlaps<false>(xs, xe, n, y0, y1);
-        }
-        if (__any(h)) return true;
-    }
-    return false;
-}
-
-// Does every element of Y lie inside one interval of the resident F list?
-__device__ bool all_inside_f(const Res &x, const VList &Y, uint32_t lane) {
-    for (uint32_t j0 = 0; j0 < Y.n; j0 += 64) {
-        const uint32_t j = j0 + lane;
-        bool miss = false;
-        if (j < Y.n) {
-            uint32_t y0, y1;
-            element(Y, j, y0, y1);
-            miss = !(x.lds ? inside<true>(x.fs, x.fe, x.nf, y0, y1) : inside<false>(x.fs, x.fe, x.nf, y0, y1));
-        }
-        if (__any(miss)) return false;
-    }
-    return true;
-}
 
 // Does any interval of Y overlap a cell of the sorted cell-id list C (as
 // [c, c+1))?  The first cell >= y0 decides for element [y0, y1).  C is in
-// LDS (cells_lds) or global memory.  Whole wave.
+// LDS (in_lds) or global memory.  Whole wave.
 template <bool LDS>
 __device__ __forceinline__ bool cell_hit(const uint32_t *c, uint32_t n, uint32_t y0, uint32_t y1) {
     uint32_t lo = 0, hi = n;
@@ -160,40 +85,7 @@ __device__ __forceinline__ VList list_of(const uint64_t *off, const uint32_t *s,
     return VList{s + a, e ? e + a : nullptr, uint32_t(b - a)};
 }
 
-// Make an object's A and F lists searchable: copied into this wave's LDS
-// (layout A.start | A.end | F.start | F.end, kTile words each) when both
-// fit, else left in global memory.
-__device__ Res stage(const VList &A, const VList &F, uint32_t *lds, uint32_t lane) {
-    Res x;
-    x.na = A.n;
-    x.nf = F.n;
-    x.lds = A.n <= kTile && F.n <= kTile;
-    if (!x.lds) {
-        x.as = A.s;
-        x.ae = A.e;
-        x.fs = F.s;
-        x.fe = F.e;
-        return x;
-    }
-    wave_lds_sync();   // the previous pair's searches are done
-    for (uint32_t i = lane; i < A.n; i += 64) {
-        lds[i] = gl(A.s, i);
-        lds[kTile + i] = gl(A.e, i);
-    }
-    for (uint32_t i = lane; i < F.n; i += 64) {
-        lds[2 * kTile + i] = gl(F.s, i);
-        lds[3 * kTile + i] = gl(F.e, i);
-    }
-    wave_lds_sync();
-    x.as = lds;
-    x.ae = lds + kTile;
-    x.fs = lds + 2 * kTile;
-    x.fe = lds + 3 * kTile;
-    return x;
-}
-
-template <uint32_t MODE>
-__global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
+__global__ __launch_bounds__(kBlock) void k_linestrings(VArgs a) {
     __shared__ uint32_t lds_all[kWavesPerBlock][4 * kTile];
     const uint32_t lane = threadIdx.x & 63;
     uint32_t *lds = lds_all[threadIdx.x >> 6];
@@ -205,14 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
         uint8_t v;
         if (r >= a.n_r || s >= a.n_s) {
             v = APRIL_BAD_PAIR;
-        } else if (MODE == kWithin) {
-            // s resident (its A for AA, its F for containment); A(r) streamed
-            const VList Ar = list_of(a.offAr, a.sAr, a.eAr, r);
-            const Res xs = stage(list_of(a.offAs, a.sAs, a.eAs, s), list_of(a.offFs, a.sFs, a.eFs, s), lds, lane);
-            v = !any_overlap(xs, false, Ar, lane) ? APRIL_TN
-                : all_inside_f(xs, Ar, lane)       ? APRIL_TH
-                                                   : APRIL_INDECISIVE;
-        } else if (MODE == kLinestring) {
+        } else {
             // the linestring's cells searched (in LDS when at most 4 kTile
             // of them: a linestring has more cells than a polygon has
             // intervals); the polygon's A- and F-lists streamed
@@ -241,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_variant(VArgs a) {
     }
 }
 
-int launch_variant(uint32_t mode, VArgs a, unsigned long long *counts, hipStream_t stream) {
+int launch_linestrings(VArgs a, unsigned long long *counts, hipStream_t stream) {
     DeviceState *st = nullptr;
     if (int rc = device_state(&st)) return rc;
     void *ws = nullptr;
@@ -257,10 +142,7 @@ int launch_variant(uint32_t mode, VArgs a, unsigned long long *counts, hipStream
     if (e == hipSuccess && a.n_pairs) {
         const uint64_t waves = std::min<uint64_t>(a.n_pairs, uint64_t(st->cus) * 32);
         const uint32_t blocks = uint32_t((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-        switch (mode) {
-            case kWithin: k_variant<kWithin><<<blocks, kBlock, 0, stream>>>(a); break;
-            default: k_variant<kLinestring><<<blocks, kBlock, 0, stream>>>(a); break;
-        }
+        k_linestrings<<<blocks, kBlock, 0, stream>>>(a);
         e = hipGetLastError();
     }
     if (e == hipSuccess && counts) {
@@ -298,14 +180,26 @@ VArgs base_args(const april_lists_t *R, const uint32_t *d_r, const uint32_t *d_s
     return a;
 }
 
-void set_s(VArgs &a, const april_lists_t *S) {
-    a.offAs = S->d.off_a;
-    a.offFs = S->d.off_f;
-    a.sAs = S->d.start_a;
-    a.eAs = S->d.end_a;
-    a.sFs = S->d.start_f;
-    a.eFs = S->d.end_f;
-    a.n_s = S->n;
+// Within joins and mixed orders on the filter's batched kernel, with a
+// stream-ordered workspace.
+int run_batched(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
+                uint64_t n_pairs, uint8_t *d_verdict, uint64_t *d_counts, hipStream_t stream, uint32_t shift_r,
+                uint32_t shift_s, bool within) {
+    if (n_pairs >= (1ull << 32)) return fail(APRIL_E_INVALID, "fewer than 2^32 pairs per call");
+    DeviceState *st = nullptr;
+    if (int rc = device_state(&st)) return rc;
+    int cur = 0;
+    APRIL_HIP_TRY(hipGetDevice(&cur));
+    if (cur != R->device) return fail(APRIL_E_INVALID, "current device does not hold the lists");
+    const FilterArgs fa =
+        make_args(R, S, d_r, d_s, n_pairs, d_verdict, reinterpret_cast<unsigned long long *>(d_counts));
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, batched_workspace_bytes(n_pairs), stream);
+    if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    const int rc = within ? launch_batched_within(fa, st->cus, ws, stream)
+                          : launch_batched_mixed(fa, shift_r, shift_s, st->cus, ws, stream);
+    APRIL_HIP_TRY(hipFreeAsync(ws, stream));
+    return rc;
 }
 
 }  // namespace
@@ -323,10 +217,8 @@ extern "C" int april_filter_within(const april_lists_t *R, const april_lists_t *
     if (!same_grid(R->grid, S->grid) || R->partition_key != S->partition_key)
         return fail(APRIL_E_GRID, "R and S lists use different grids");
     if (n_pairs && (!d_r || !d_s || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
-    VArgs a = base_args(R, d_r, d_s, n_pairs, d_verdict);
-    set_s(a, S);
-    return launch_variant(kWithin, a, reinterpret_cast<unsigned long long *>(d_counts),
-                          static_cast<hipStream_t>(hip_stream));
+    return run_batched(R, S, d_r, d_s, n_pairs, d_verdict, d_counts, static_cast<hipStream_t>(hip_stream), 0, 0,
+                       true);
 }
 
 extern "C" int april_filter_linestrings(const april_lists_t *P, const april_cells_t *L, const uint32_t *d_p,
@@ -343,7 +235,7 @@ extern "C" int april_filter_linestrings(const april_lists_t *P, const april_cell
     a.offAs = L->d_off;
     a.sAs = L->d_ids;
     a.n_s = L->n;
-    return launch_variant(kLinestring, a, reinterpret_cast<unsigned long long *>(d_counts),
+    return launch_linestrings(a, reinterpret_cast<unsigned long long *>(d_counts),
                           static_cast<hipStream_t>(hip_stream));
 }
 
@@ -366,18 +258,6 @@ extern "C" int april_filter_mixed(const april_lists_t *R, const april_lists_t *S
         o.schedule = APRIL_SCHED_BATCHED;
         return april_filter_pairs(R, S, d_r, d_s, n_pairs, d_verdict, d_counts, &o, hip_stream);
     }
-    if (n_pairs >= (1ull << 32)) return fail(APRIL_E_INVALID, "fewer than 2^32 pairs per call");
-    DeviceState *st = nullptr;
-    if (int rc = device_state(&st)) return rc;
-    int cur = 0;
-    APRIL_HIP_TRY(hipGetDevice(&cur));
-    if (cur != R->device) return fail(APRIL_E_INVALID, "current device does not hold the lists");
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
-    const FilterArgs fa = make_args(R, S, d_r, d_s, n_pairs, d_verdict, reinterpret_cast<unsigned long long *>(d_counts));
-    void *ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, batched_workspace_bytes(n_pairs), stream);
-    if (e != hipSuccess) return fail(APRIL_E_NOMEM, std::string("workspace: ") + hipGetErrorString(e));
-    const int rc = launch_batched_mixed(fa, shift_r, shift_s, st->cus, ws, stream);
-    APRIL_HIP_TRY(hipFreeAsync(ws, stream));
-    return rc;
+    return run_batched(R, S, d_r, d_s, n_pairs, d_verdict, d_counts, static_cast<hipStream_t>(hip_stream), shift_r,
+                       shift_s, false);
 }

@@ -8,7 +8,8 @@ Cases:
     candidate pair against the oracle's filter run on the library's lists
     (the library's builders are pinned against the oracle's elsewhere);
   * mixed orders both ways (R finer, S finer), and one order, which must
-    equal april_filter_pairs;
+    equal april_filter_pairs; orders 16 x 15 both ways, where thousands of
+    coarse objects are loaded in pieces;
   * edge cases: no pairs, ids out of range, grids that do not match.
 """
 
@@ -154,6 +155,27 @@ def test_mixed_scale(scale):
     want = oracle.filter_mixed(as_oracle(hR), 16, as_oracle(hS), 14, r, s)
     got, cnt = run(april.april_filter_mixed, dev(hR), dev(hS), r, s)
     check(got, cnt, want)
+
+
+def test_mixed_pieces_both_ways(scale):
+    """Orders 16 x 15: thousands of coarse objects have lists longer than a
+    tile, so the resident coarse side is cut into pieces.  Every pair whose
+    coarse object needs pieces, plus a random sample of the others."""
+    R, S, _, _, _, r, s = scale
+    gf, gc = synth.configs.two_orders(R, S, 16, 15)
+    rng = np.random.default_rng(12)
+    for name, gR, gS in (("R fine", gf, gc), ("S fine", gc, gf)):
+        hR, hS = host_lists(gR, R), host_lists(gS, S)
+        coarse = hS if gR is gf else hR
+        e = coarse.export()
+        big = np.maximum(np.diff(e[0]), np.diff(e[3])) >= 256
+        sel = big[s] if gR is gf else big[r]
+        pick = np.nonzero(sel | (rng.random(len(r)) < 0.02))[0]
+        assert sel.sum() > 1000
+        say(f"[mixed] 16 x 15 {name}: {int(sel.sum())} pairs with a coarse object in pieces, {len(pick)} checked")
+        want = oracle.filter_mixed(as_oracle(hR), gR.order, as_oracle(hS), gS.order, r[pick], s[pick])
+        got, cnt = run(april.april_filter_mixed, dev(hR), dev(hS), r[pick], s[pick])
+        check(got, cnt, want)
 
 
 # ----------------------------------------------------------------- edges

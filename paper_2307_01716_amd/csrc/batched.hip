@@ -59,8 +59,9 @@ namespace april {
 namespace {
 
 // Join modes of the kernel: Alg. 2 on one grid; Alg. 2 across two orders
-// (Sec. 5.3); within joins (Sec. 4.3.2).
-constexpr int kAlg2 = 0, kMixedOrders = 1, kWithinJoin = 2;
+// (Sec. 5.3); within joins
+// (Sec. 4.3.2); polygon-linestring joins (Sec. 4.3.3).
+constexpr int kAlg2 = 0, kMixedOrders = 1, kWithinJoin = 2, kLinestrings = 3;
 
 constexpr uint32_t kSideS = 0x80000000u;   // resident-object key: the object is from S
 constexpr uint32_t kNone = 0xffffffffu;    // no resident object / no upper key bound
@@ -193,11 +194,13 @@ __device__ __forceinline__ void load_resident(const Resident &x, const uint32_t 
 // FA, each element that overlaps the A-list is also tested against the
 // resident F-list, and an overlap there sets *th and ends the scan.
 //
-// With MIX the streamed list is the finer side's A-list and each element is
-// mapped to the resident (coarser) grid as it is read: [s >> sh,
-// ((e - 1) >> sh) + 1).  Mapped elements stay sorted by start and by end
-// (they may touch or overlap each other), which is all the scan needs.
-template <int TILE, int C, bool FA, bool MIX>
+// MAP says how a streamed element is read: kAsIs; kShifted, the finer
+// side's A-interval mapped to the resident (coarser) grid as [s >> sh,
+// ((e - 1) >> sh) + 1), mapped elements staying sorted by start and by end
+// (they may touch or overlap each other), which is all the scan needs; or
+// kUnitCells, a cell id c taken as [c, c + 1) (ye is not read).
+constexpr int kAsIs = 0, kShifted = 1, kUnitCells = 2;
+template <int TILE, int C, bool FA, int MAP>
 __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *__restrict__ ys,
                                              const uint32_t *__restrict__ ye, uint32_t j, uint32_t m,
                                              uint32_t stop, uint32_t lane, bool *th, uint32_t sh) {
@@ -209,8 +212,12 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
             // lanes past the end load nothing and take an empty [0, 0)
             const uint32_t k = j + c * 64 + lane;
             s[c] = k < m ? gload(ys, k) : 0u;
-            e[c] = k < m ? gload(ye, k) : 0u;
-            if (MIX) {
+            if (MAP == kUnitCells) {
+                e[c] = k < m ? s[c] + 1 : 0u;
+            } else {
+                e[c] = k < m ? gload(ye, k) : 0u;
+            }
+            if (MAP == kShifted) {
                 s[c] >>= sh;
                 e[c] = k < m ? ((e[c] - 1) >> sh) + 1 : 0u;
             }
@@ -288,6 +295,8 @@ struct PairLists {
 //
 // kMixedOrders: Y is the finer side's A-list mapped to X's grid (shift sh),
 // and only the coarse side's F decides a true hit (Sec. 5.3): no AF pass.
+// kLinestrings: X is the polygon, Y the linestring's cell ids as unit
+// intervals; the first pass decides (a cell inside F(p): a true hit).
 // kWithinJoin: X is s, Y is A(r); bit 0 of the result is an AA overlap in
 // this piece, bit 1 that every element of A(r) meeting [k0, k1) lies inside
 // one F(s) interval; `want` says which of the two to find (a piece answers
@@ -295,17 +304,19 @@ struct PairLists {
 template <int TILE, int C, int MODE>
 __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLists &L, uint32_t k0, uint32_t k1,
                                                uint32_t search_min, uint32_t lane, uint32_t sh, uint32_t want) {
-    constexpr bool MIX = MODE == kMixedOrders;
+    constexpr int MAP = MODE == kMixedOrders ? kShifted : MODE == kLinestrings ? kUnitCells : kAsIs;
     // Y elements that can meet this piece: end above x_lo, start below x_hi
     const uint32_t x_lo = max(k0, uniform(res.as[0]));
     const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
     const bool narrow = k0 > 0;
     bool th = false;
     // a mapped end ((e - 1) >> sh) + 1 is above x_lo iff e is above x_lo << sh
-    const uint32_t ja =
-        (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, MIX ? x_lo << sh : x_lo, lane)) : 0;
+    // (a unit cell c ends above x_lo iff c >= x_lo, i.e. c > x_lo - 1)
+    const uint32_t ja = !(narrow || L.nya > search_min) || (MAP == kUnitCells && x_lo == 0) ? 0
+                        : MAP == kUnitCells ? uniform(wave_first_above(L.yas, L.nya, x_lo - 1, lane))
+                                            : uniform(wave_first_above(L.yae, L.nya, MAP == kShifted ? x_lo << sh : x_lo, lane));
     if (MODE == kWithinJoin) {
-        const bool aa = (want & 1) && stream_piece<TILE, C, false, false>(res, L.yas, L.yae, ja, L.nya, x_hi, lane,
+        const bool aa = (want & 1) && stream_piece<TILE, C, false, kAsIs>(res, L.yas, L.yae, ja, L.nya, x_hi, lane,
                                                                           &th, 0);
         if ((want & 1) && !aa && !narrow && k1 == kNone) return 0;   // one piece and no overlap
         bool in = false;
@@ -317,11 +328,11 @@ __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLi
         }
         return (aa ? 1u : 0u) | (in ? 2u : 0u);
     }
-    if (!stream_piece<TILE, C, true, MIX>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th, sh)) return 0;
+    if (!stream_piece<TILE, C, true, MAP>(res, L.yas, L.yae, ja, L.nya, x_hi, lane, &th, sh)) return 0;
     if (th) return 1;
-    if (MIX) return 2;
+    if (MODE == kMixedOrders || MODE == kLinestrings) return 2;
     const uint32_t jf = (narrow || L.nyf > search_min) ? uniform(wave_first_above(L.yfe, L.nyf, x_lo, lane)) : 0;
-    return stream_piece<TILE, C, false, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th, 0) ? 1 : 2;
+    return stream_piece<TILE, C, false, kAsIs>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, lane, &th, 0) ? 1 : 2;
 }
 
 // Alg. 2's verdict for one pair, by the whole wave.  When both of X's lists
@@ -494,10 +505,12 @@ void k_batched(BatchArgs b) {
                     // R resident when its lists fit a tile; else S when its
                     // do or when neither does and S's are shorter
                     // (mixed orders: the coarser side, whose lists stay
-                    // sorted and disjoint; within joins: s, the container)
+                    // sorted and disjoint; within joins: s, the container;
+                    // linestrings: the polygon)
                     const bool xs = MODE == kMixedOrders ? pb->shift_r != 0
                                     : MODE == kWithinJoin ? true
-                                                          : !(mr < TILE) && (ms < TILE || ms < mr);
+                                    : MODE == kLinestrings ? false
+                                                           : !(mr < TILE) && (ms < TILE || ms < mr);
                     if (MODE == kAlg2 && max(mr, ms) <= pb->thread_max) seq = true;
                     else wave = true;
                     m = pair_lists(a, xs, ar0, nar, fr0, nfr, as0, nas, fs0, nfs);
@@ -671,6 +684,21 @@ int launch_batched_within(const FilterArgs &a, int cus, void *workspace, hipStre
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     return launch_tc<256, 2, kWithinJoin>(b, cus, 0, stream);
+}
+
+int launch_batched_linestrings(const FilterArgs &a, int cus, void *workspace, hipStream_t stream) {
+    BatchArgs b;
+    b.f = a;
+    b.xhead = static_cast<unsigned int *>(workspace);
+    b.xcds = uint32_t(xcd_count(cus));
+    b.thread_max = 0;   // unused: every pair by the wave
+    b.search_min = 512;
+    b.grab = 32;
+    b.tail_grab = 8;
+    b.shift_r = b.shift_s = 0;
+    k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
+    APRIL_HIP_TRY(hipGetLastError());
+    return launch_tc<256, 2, kLinestrings>(b, cus, 0, stream);
 }
 
 }  // namespace april

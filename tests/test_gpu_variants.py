@@ -10,6 +10,8 @@ Cases:
   * mixed orders both ways (R finer, S finer), and one order, which must
     equal april_filter_pairs; orders 16 x 15 both ways, where thousands of
     coarse objects are loaded in pieces;
+  * polygons whose lists are longer than a tile (loaded in pieces) against
+    linestrings;
   * edge cases: no pairs, ids out of range, grids that do not match.
 """
 
@@ -122,7 +124,10 @@ def test_linestrings_scale():
     hP = host_lists(g, P)
     hC = april.april_build_cells(g, L.xy, L.voff, april.STRICT)
     p, l = linestring_pairs(P, L)
-    say(f"[linestrings] scale {len(p)} pairs")
+    e = hP.export()
+    big = (np.maximum(np.diff(e[0]), np.diff(e[3])) >= 256)[p]
+    say(f"[linestrings] scale {len(p)} pairs, {int(big.sum())} with the polygon in pieces")
+    assert big.sum() > 1000
     off, ids = hC.export()
     want = oracle.filter_linestrings(as_oracle(hP), oracle.Cells(off, ids), p, l)
     got, cnt = run(april.april_filter_linestrings, dev(hP), april.april_cells_to_device(hC), p, l)
@@ -191,6 +196,14 @@ def test_edge_cases():
         ss = np.array([s[0], 0, len(S) + 3, 1], np.uint32)
         got, cnt = run(fn, dR, dS, rr, ss)
         assert list(got[1:]) == [april.BAD_PAIR] * 3 and cnt.sum() == 1
+    P, L, gl = synth.configs.linestring_scale(n_poly=300, n_lines=300)
+    dP = dev(host_lists(gl, P))
+    dC = april.april_cells_to_device(april.april_build_cells(gl, L.xy, L.voff, april.STRICT))
+    got, cnt = run(april.april_filter_linestrings, dP, dC, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert len(got) == 0 and list(cnt) == [0, 0, 0]
+    got, cnt = run(april.april_filter_linestrings, dP, dC, np.array([0, 300, 7, 0xFFFFFFFF], np.uint32),
+                   np.array([0, 0, 300, 1], np.uint32))
+    assert list(got[1:]) == [april.BAD_PAIR] * 3 and cnt.sum() == 1
     from synth.polygons import LATTICE
     w = g.cell_lattice * LATTICE
     other = synth.Grid(g.x0 - w, g.y0 - w, g.side, g.order)   # origin one cell off

@@ -102,16 +102,21 @@ __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t
                 wave_lds_sync();
                 const uint32_t k = vdecode_window(cy, ys, ye, true, lane);
                 wave_lds_sync();
-                bool hit = false;
-                for (uint32_t t = lane; t < k; t += 64) {
-                    const uint32_t s = ys[t], e = ye[t];
-                    uint32_t pos = 0;
-                    for (uint32_t step = 1u << (31 - __builtin_clz(nt)); step; step >>= 1) {
-                        const uint32_t q = pos + step;
-                        if (q <= nt && te[q - 1] <= s) pos = q;
-                    }
-                    hit |= pos < nt && ts[pos] < e;
+                // a window completes at most 128 intervals: lane l tests
+                // intervals l and l + 64, both searches interleaved; one
+                // outside [x_lo, x_hi) cannot meet the tile and is empty
+                const bool v0 = lane < k, v1 = lane + 64 < k;
+                uint32_t s0 = v0 ? ys[lane] : 0u, e0 = v0 ? ye[lane] : 0u;
+                uint32_t s1 = v1 ? ys[lane + 64] : 0u, e1 = v1 ? ye[lane + 64] : 0u;
+                if (e0 <= x_lo || s0 >= x_hi) e0 = s0 = 0;
+                if (e1 <= x_lo || s1 >= x_hi) e1 = s1 = 0;
+                uint32_t p0 = 0, p1 = 0;
+                for (uint32_t step = 1u << (31 - __builtin_clz(nt)); step; step >>= 1) {
+                    const uint32_t q0 = p0 + step, q1 = p1 + step;
+                    if (q0 <= nt && te[q0 - 1] <= s0) p0 = q0;
+                    if (q1 <= nt && te[q1 - 1] <= s1) p1 = q1;
                 }
+                const bool hit = (p0 < nt && ts[p0] < e0) || (p1 < nt && ts[p1] < e1);
                 if (__any(hit)) return true;
                 // every later Y interval starts after this tile ends
                 if (k == 0 || ys[k - 1] >= x_hi) break;

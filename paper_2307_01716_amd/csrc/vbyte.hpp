@@ -29,26 +29,31 @@ struct VCursor {
     uint32_t g;            // values decoded so far
 };
 
-__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane) {
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d);
-        if (lane >= uint32_t(d)) x += y;
-    }
-    return x - v;
+// Cross-lane steps on DPP (VALU operand routing, no trip through the LDS
+// unit): every lane of the wave must be active.
+//
+// Inclusive prefix sum over the wave: a scan within each row of 16 lanes by
+// shifts of 1, 2, 4 and 8 lanes (lanes shifted in from outside the row read
+// 0), then lane 15 of a row added to the row above it (rows 1 and 3), and
+// lane 31 to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xf, 0xf, true);    // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xf, 0xf, true);    // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xf, 0xf, true);    // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xf, 0xf, true);    // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return x;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d);
-    return v;
+// Lane l receives lane l - 1's value (lane 0 receives 0).
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t v) {
+    return __builtin_amdgcn_update_dpp(0u, v, 0x138, 0xf, 0xf, false);   // wave_shr:1
 }
 
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d));
-    return v;
+// Lane l receives lane l + 1's value (lane 63 receives 0).
+__device__ __forceinline__ uint32_t from_lane_above(uint32_t v) {
+    return __builtin_amdgcn_update_dpp(0u, v, 0x130, 0xf, 0xf, false);   // wave_shl:1
 }
 
 // Cursor at interval 0 of a list.
@@ -74,6 +79,50 @@ __device__ __forceinline__ VCursor vcursor_block(const uint8_t *bytes, uint64_t 
     return c;
 }
 
+// The values that start in one lane's four bytes of a window.
+struct LaneVals {
+    uint32_t starts;     // bit k: a value starts at byte k of the lane's word
+    uint32_t nval;       // number of such values
+    uint32_t local;      // sum of (delta + 1) over them
+    uint32_t last_end;   // window byte of the last one's last byte
+    uint32_t cum[4];     // cum[k]: the running sum up to and including byte k's value
+};
+
+// Per-lane part of a window's decoding, branch-free arithmetic (also built
+// for the host).  w is the lane's word (window bytes 4 lane .. 4 lane + 3),
+// wn the next word and wprev the one before; the window's values start at
+// window byte `first` and the stream ends before window byte `stop`.
+__host__ __device__ __forceinline__ LaneVals vdecode_lane(uint32_t w, uint32_t wn, uint32_t wprev, uint32_t lane,
+                                                          uint32_t first, uint32_t stop) {
+    const uint64_t x = uint64_t(w) | (uint64_t(wn) << 32);
+    // bit 8k + 7: byte k - 1 (for k = 0, byte 3 of the word before) has its
+    // high bit clear, i.e. ends a value, so byte k starts one
+    const uint32_t after_end = ((~w & 0x80808080u) << 8) | ((~wprev & 0x80000000u) >> 24);
+    LaneVals r{0u, 0u, 0u, 0u, {0u, 0u, 0u, 0u}};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const uint32_t b = 4 * lane + uint32_t(k);
+        const bool st = b >= first && b < stop && (b == first || ((after_end >> (8 * k + 7)) & 1u));
+        // the value at byte k: 7-bit groups of bytes k .. k + 4, low group
+        // first, cut after its first byte with the high bit clear (byte t)
+        const uint32_t y = uint32_t(x >> (8 * k));
+        const uint32_t y4 = uint32_t(x >> (8 * k + 32)) & 0xffu;
+        uint32_t v = (y & 0x7fu) | ((y >> 1) & 0x3f80u) | ((y >> 2) & 0x1fc000u) | ((y >> 3) & 0xfe00000u) |
+                     (y4 << 28);
+        const uint32_t term = ~y & 0x80808080u;
+        const uint32_t t = term ? uint32_t(__builtin_ctz(term)) >> 3 : 4u;
+        if (t < 4) v &= (1u << (7 * t + 7)) - 1u;
+        if (st) {
+            r.local += v + 1u;
+            r.cum[k] = r.local;
+            r.last_end = b + t;
+            r.starts |= 1u << k;
+            r.nval++;
+        }
+    }
+    return r;
+}
+
 // Decode one window.  Interval t of the window (t = 0 is the interval whose
 // start was pending, if any) goes to (bs[t], be[t]); returns the number of
 // intervals completed, k (their ends are all written).  The start of the
@@ -89,62 +138,33 @@ __device__ __forceinline__ uint32_t vdecode_window(VCursor &c, uint32_t *bs, uin
     const uint32_t skip = uint32_t(reinterpret_cast<uintptr_t>(p) - a);     // bytes before the value start
     const uint32_t *wp = reinterpret_cast<const uint32_t *>(a);
     const uint32_t w = wp[lane];
-    uint32_t wn = __shfl_down(w, 1);
+    uint32_t wn = from_lane_above(w);
     if (lane == 63) wn = wp[64];
-    const uint32_t wprev = __shfl_up(w, 1);
-    const uint64_t x = uint64_t(w) | (uint64_t(wn) << 32);
-    // byte positions relative to the value start p: 4*lane + k - skip
-    uint32_t starts = 0;   // bit k: a value starts at byte k of this lane's word
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const int rel = int(4 * lane + k) - int(skip);
-        const bool valid = rel >= 0 && uint32_t(rel) < c.nbytes - c.pos;
-        uint32_t before;
-        if (k > 0) before = (w >> (8 * (k - 1))) & 0xffu;
-        else before = (wprev >> 24) & 0xffu;
-        const bool st = valid && (rel == 0 || before < 0x80u);
-        starts |= uint32_t(st) << k;
-    }
-    // decode the values that start here
-    uint32_t vals[4], nval = 0, last_end = 0, local = 0;
-    uint32_t cum[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        if ((starts >> k) & 1u) {
-            uint32_t v = 0, t = 0;
-#pragma unroll
-            for (int u = 0; u < 5; u++) {
-                const uint32_t b = uint32_t(x >> (8 * (k + u))) & 0xffu;
-                if (u == t) {
-                    v |= (b & 0x7fu) << (7 * u);
-                    if (b >= 0x80u) t++;
-                }
-            }
-            last_end = 4 * lane + k + t;     // window byte of the value's last byte
-            local += v + 1u;
-            vals[nval] = v;
-            cum[nval] = local;
-            nval++;
-        }
-    }
-    (void)vals;
-    const uint32_t before_vals = wave_excl_scan(nval, lane);
-    const uint32_t V = wave_sum(nval);
-    const uint32_t before_sum = wave_excl_scan(local, lane);
-    const uint32_t total = wave_sum(local);
+    const uint32_t wprev = from_lane_below(w);
+    // a window spans 256 bytes (+4 seen by lane 63)
+    const uint32_t avail = c.nbytes - c.pos;
+    const LaneVals L = vdecode_lane(w, wn, wprev, lane, skip, skip + (avail < 512u ? avail : 512u));
+    const uint32_t inc_vals = wave_incl_scan(L.nval), inc_sum = wave_incl_scan(L.local);
+    const uint32_t before_vals = inc_vals - L.nval, before_sum = inc_sum - L.local;
+    const uint32_t V = __builtin_amdgcn_readlane(inc_vals, 63);
+    const uint32_t total = __builtin_amdgcn_readlane(inc_sum, 63);
     const uint32_t g0 = c.g, i0 = g0 >> 1;
     if (write_pending && lane == 0 && (g0 & 1u)) bs[0] = c.prev;
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        if (uint32_t(j) < nval) {
-            const uint32_t gv = g0 + before_vals + j;
-            const uint32_t absv = c.prev + before_sum + cum[j];
+    for (int k = 0; k < 4; k++) {
+        if ((L.starts >> k) & 1u) {
+            const uint32_t gv = g0 + before_vals + uint32_t(__builtin_popcount(L.starts & ((1u << k) - 1u)));
+            const uint32_t absv = c.prev + before_sum + L.cum[k];
             const uint32_t i = (gv >> 1) - i0;
             if (gv & 1u) be[i] = absv;
             else bs[i] = absv;
         }
     }
-    const uint32_t end_byte = wave_max(nval ? last_end + 1 : 0u);   // window-relative
+    // one past the window byte where the last value ends: values in higher
+    // lanes end later, so the highest lane holding a value has it
+    const uint64_t holds = __ballot(L.nval != 0);
+    const uint32_t end_byte =
+        holds ? __builtin_amdgcn_readlane(L.last_end + 1, 63 - __builtin_clzll(holds)) : 0u;   // window-relative
     c.pos += end_byte - skip;
     c.prev += total;
     c.g += V;

@@ -37,6 +37,7 @@ struct CArgs {
     unsigned int *xhead;
     uint32_t xcds;
     uint32_t search_min;
+    uint32_t first_cap;   // X intervals decoded before a join's first test (at most TILE)
 };
 
 __device__ __forceinline__ uint32_t first_gt(const uint32_t *__restrict__ arr, uint32_t m, uint32_t key,
@@ -74,17 +75,18 @@ __device__ __forceinline__ VCursor cursor_at(const ListRef &x) {
 // Any overlap between list X (tiled through LDS) and list Y (streamed)?
 template <int TILE>
 __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t *te, uint32_t *ys,
-                      uint32_t *ye, uint32_t search_min, uint32_t lane) {
+                      uint32_t *ye, uint32_t search_min, uint32_t first_cap, uint32_t lane) {
     if (X.n == 0 || Y.n == 0) return false;
     VCursor cx = cursor_at(X);
     const uint64_t yb0 = Y.L.boff[Y.obj], yb1 = Y.L.boff[Y.obj + 1];
     const uint64_t yblk = Y.L.blk[Y.obj];
     const uint32_t ynblk = uint32_t(Y.L.blk[Y.obj + 1] - yblk);
+    uint32_t cap = first_cap;   // a short first tile: a join that ends early decodes less of X
     while (cx.g < cx.nvals) {
         // fill the tile window by window (a window completes at most 128
         // intervals and may leave one start pending after them)
         uint32_t nt = 0;
-        while (cx.g < cx.nvals && nt + 130 <= TILE) {
+        while (cx.g < cx.nvals && nt + 130 <= cap) {
             wave_lds_sync();
             nt += vdecode_window(cx, ts + nt, te + nt, false, lane);
         }
@@ -122,6 +124,7 @@ __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t
                 if (k == 0 || ys[k - 1] >= x_hi) break;
             }
         }
+        cap = TILE;
         // a start decoded after the tile's last full interval opens the next tile
         if (cx.g & 1u) {
             const uint32_t pend = ts[nt];
@@ -167,9 +170,9 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                 const ListRef YA{xs ? a.Ar : a.As, xs ? r : s, xs ? nar : nas};
                 const ListRef YF{xs ? a.Fr : a.Fs, xs ? r : s, xs ? nfr : nfs};
                 uint8_t v;
-                if (!cjoin<TILE>(XA, YA, ts, te, ys, ye, a.search_min, lane)) v = APRIL_TN;
-                else if (cjoin<TILE>(XA, YF, ts, te, ys, ye, a.search_min, lane) ||
-                         cjoin<TILE>(XF, YA, ts, te, ys, ye, a.search_min, lane))
+                if (!cjoin<TILE>(XA, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane)) v = APRIL_TN;
+                else if (cjoin<TILE>(XA, YF, ts, te, ys, ye, a.search_min, a.first_cap, lane) ||
+                         cjoin<TILE>(XF, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane))
                     v = APRIL_TH;
                 else v = APRIL_INDECISIVE;
                 if (lane == 0) {
@@ -242,6 +245,10 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
     k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     const uint32_t tile = o.tile ? o.tile : 512;
+    // chunk: windows (up to 130 intervals each) in a join's first tile
+    if (o.chunk > 4) return fail(APRIL_E_INVALID, "compressed lists: chunk must be 0 to 4");
+    // (one by default: most joins of overlapping objects end within it)
+    a.first_cap = std::min<uint32_t>(tile, 130u * (o.chunk ? o.chunk : 1u));
     const uint64_t blocks = uint64_t(cus) * 8;
     switch (tile) {
         case 256: k_filter_vbyte<256><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;

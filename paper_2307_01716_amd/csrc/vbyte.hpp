@@ -102,7 +102,7 @@ __host__ __device__ __forceinline__ LaneVals vdecode_lane(uint32_t w, uint32_t w
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const uint32_t b = 4 * lane + uint32_t(k);
-        const bool st = b >= first && b < stop && (b == first || ((after_end >> (8 * k + 7)) & 1u));
+        const bool st = (b >= first) & (b < stop) & ((b == first) | bool((after_end >> (8 * k + 7)) & 1u));
         // the value at byte k: 7-bit groups of bytes k .. k + 4, low group
         // first, cut after its first byte with the high bit clear (byte t)
         const uint32_t y = uint32_t(x >> (8 * k));
@@ -112,13 +112,12 @@ __host__ __device__ __forceinline__ LaneVals vdecode_lane(uint32_t w, uint32_t w
         const uint32_t term = ~y & 0x80808080u;
         const uint32_t t = term ? uint32_t(__builtin_ctz(term)) >> 3 : 4u;
         if (t < 4) v &= (1u << (7 * t + 7)) - 1u;
-        if (st) {
-            r.local += v + 1u;
-            r.cum[k] = r.local;
-            r.last_end = b + t;
-            r.starts |= 1u << k;
-            r.nval++;
-        }
+        // selects, not branches: every byte position is worked out
+        r.local += st ? v + 1u : 0u;
+        r.cum[k] = r.local;
+        r.last_end = st ? b + t : r.last_end;
+        r.starts |= uint32_t(st) << k;
+        r.nval += uint32_t(st);
     }
     return r;
 }

@@ -74,8 +74,9 @@ def test_round_trip(spread):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("tile,search_min", [(256, 1), (512, 1024), (1024, 64)])
-def test_random_lists_compressed(tile, search_min):
+@pytest.mark.parametrize("tile,search_min,chunk", [(256, 1, 0), (512, 1024, 0), (1024, 64, 0), (512, 64, 1),
+                                                    (1024, 1024, 2), (256, 1, 4)])
+def test_random_lists_compressed(tile, search_min, chunk):
     rng = np.random.default_rng(tile + search_min)
     n = 160
     lens = rng.choice([1, 5, 60, 64, 65, 130, 300, 1500, 9000], n)
@@ -85,12 +86,12 @@ def test_random_lists_compressed(tile, search_min):
     r = rng.integers(0, n, P).astype(np.uint32)
     s = rng.integers(0, n, P).astype(np.uint32)
     want = oracle.filter_pairs(LR, LS, r, s)
-    say(f"[vbyte] filter tile={tile} search_min={search_min} P={P}")
+    say(f"[vbyte] filter tile={tile} search_min={search_min} chunk={chunk} P={P}")
     dR, dS = upload(GRID, LR, april.CODEC_VBYTE), upload(GRID, LS, april.CODEC_VBYTE)
     v = torch.empty(P, dtype=torch.uint8, device="cuda")
     c = torch.empty(3, dtype=torch.int64, device="cuda")
     april.april_filter_pairs(dR, dS, cuda(r), cuda(s), v, c, schedule=april.SCHED_BATCHED, tile=tile,
-                             search_min=search_min)
+                             search_min=search_min, chunk=chunk)
     torch.cuda.synchronize()
     assert np.array_equal(v.cpu().numpy(), want)
     assert np.array_equal(c.cpu().numpy(), np.bincount(want, minlength=3))

@@ -241,8 +241,8 @@ def partitioned_bench(args):
     ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
     forms, ref = {}, None
     for codec, name, grid in ((april.CODEC_RAW, "raw", {"tile": (256, 512), "chunk": (1, 2)}),
-                              (april.CODEC_VBYTE, "vbyte", {"tile": (512, 1024),
-                                                            "chunk": (0, 1, 2)})):
+                              (april.CODEC_VBYTE, "vbyte", {"tile": (256, 512),
+                                                            "chunk": (1, 2, 4)})):
         dR = april.april_lists_to_device(hR, codec=codec, stream=stream)
         dS = april.april_lists_to_device(hS, codec=codec, stream=stream)
         torch.cuda.synchronize()

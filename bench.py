@@ -242,7 +242,7 @@ def partitioned_bench(args):
     forms, ref = {}, None
     for codec, name, grid in ((april.CODEC_RAW, "raw", {"tile": (256, 512), "chunk": (1, 2)}),
                               (april.CODEC_VBYTE, "vbyte", {"tile": (256, 512),
-                                                            "chunk": (1, 2, 4)})):
+                                                            "search_min": (64, 1024)})):
         dR = april.april_lists_to_device(hR, codec=codec, stream=stream)
         dS = april.april_lists_to_device(hS, codec=codec, stream=stream)
         torch.cuda.synchronize()

@@ -232,7 +232,7 @@ typedef struct {
                               intervals run one lane per pair (0 = 8) */
     uint32_t search_min;   /* batched: streamed lists longer than this are first narrowed
                               to the resident list's Hilbert range by a 64-ary search
-                              (0 = 512; compressed lists: 1024) */
+                              (0 = 512; compressed lists: 64) */
     uint32_t reserved;     /* must be 0 */
     void *d_workspace;     /* device scratch of april_filter_workspace_size() bytes
                               (work counters; count sums), or NULL to let the library
@@ -263,6 +263,14 @@ int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opt
  *                        whose lists are all very short run one lane per
  *                        pair.  Launches only kernels when a workspace is
  *                        passed, so it can be captured in a hipGraph.
+ *                        Compressed lists (APRIL_CODEC_VBYTE) run one
+ *                        wavefront per pair decoding as it joins; the call
+ *                        also takes a stream-ordered decode cache (64 KiB
+ *                        per wavefront, 512 MiB on 256 CUs) that keeps R
+ *                        objects of up to 4,096 intervals per list decoded
+ *                        while consecutive pairs share them (without it,
+ *                        when the allocation is refused, every pair decodes
+ *                        both objects; the verdicts are the same).
  *   R, S        device-resident lists on the same grid (else APRIL_E_GRID)
  *   d_r, d_s    device uint32[n_pairs]: pair p is (R object d_r[p], S object d_s[p])
  *   d_verdict   device uint8[n_pairs]: APRIL_TN / APRIL_TH / APRIL_INDECISIVE,

@@ -38,6 +38,11 @@ struct CArgs {
     uint32_t xcds;
     uint32_t search_min;
     uint32_t first_cap;   // X intervals decoded before a join's first test (at most TILE)
+    // decode cache: per wave, R's A and F lists of up to cache_cap intervals
+    // each, decoded once per run of pairs that share the R object (nullptr:
+    // no cache)
+    uint32_t *cache;
+    uint32_t cache_cap;
 };
 
 __device__ __forceinline__ uint32_t first_gt(const uint32_t *__restrict__ arr, uint32_t m, uint32_t key,
@@ -72,15 +77,55 @@ __device__ __forceinline__ VCursor cursor_at(const ListRef &x) {
     return vcursor(x.L.bytes, x.L.boff[x.obj], x.L.boff[x.obj + 1], x.n);
 }
 
-// Any overlap between list X (tiled through LDS) and list Y (streamed)?
+// Does Y (compressed, streamed) overlap the X tile ts/te (nt > 0 sorted,
+// disjoint intervals in LDS)?  Y is decoded from the last block whose first
+// start is at or before the tile's first start, window by window into ys/ye,
+// until a Y start reaches the tile's end.
+__device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *te, uint32_t nt, const ListRef &Y,
+                                           uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
+    const uint64_t yb0 = Y.L.boff[Y.obj], yb1 = Y.L.boff[Y.obj + 1];
+    const uint64_t yblk = Y.L.blk[Y.obj];
+    const uint32_t ynblk = uint32_t(Y.L.blk[Y.obj + 1] - yblk);
+    const uint32_t x_lo = ts[0], x_hi = te[nt - 1];
+    VCursor cy = vcursor(Y.L.bytes, yb0, yb1, Y.n);
+    if (Y.n > search_min && ynblk > 1) {
+        uint32_t b = first_gt(Y.L.bval + yblk, ynblk, x_lo, lane);
+        b = b ? b - 1 : 0;
+        if (b) cy = vcursor_block(Y.L.bytes, yb0, yb1, Y.n, b, Y.L.bval[yblk + b], Y.L.bpos[yblk + b]);
+    }
+    while (cy.g < cy.nvals) {
+        wave_lds_sync();
+        const uint32_t k = vdecode_window(cy, ys, ye, true, lane);
+        wave_lds_sync();
+        // a window completes at most 128 intervals: lane l tests intervals l
+        // and l + 64, both searches interleaved; one outside [x_lo, x_hi)
+        // cannot meet the tile and is empty
+        const bool v0 = lane < k, v1 = lane + 64 < k;
+        uint32_t s0 = v0 ? ys[lane] : 0u, e0 = v0 ? ye[lane] : 0u;
+        uint32_t s1 = v1 ? ys[lane + 64] : 0u, e1 = v1 ? ye[lane + 64] : 0u;
+        if (e0 <= x_lo || s0 >= x_hi) e0 = s0 = 0;
+        if (e1 <= x_lo || s1 >= x_hi) e1 = s1 = 0;
+        uint32_t p0 = 0, p1 = 0;
+        for (uint32_t step = 1u << (31 - __builtin_clz(nt)); step; step >>= 1) {
+            const uint32_t q0 = p0 + step, q1 = p1 + step;
+            if (q0 <= nt && te[q0 - 1] <= s0) p0 = q0;
+            if (q1 <= nt && te[q1 - 1] <= s1) p1 = q1;
+        }
+        const bool hit = (p0 < nt && ts[p0] < e0) || (p1 < nt && ts[p1] < e1);
+        if (__any(hit)) return true;
+        // every later Y interval starts after this tile ends
+        if (k == 0 || ys[k - 1] >= x_hi) break;
+    }
+    return false;
+}
+
+// Any overlap between list X (compressed, decoded tile by tile into LDS) and
+// list Y (compressed, streamed)?
 template <int TILE>
 __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t *te, uint32_t *ys,
                       uint32_t *ye, uint32_t search_min, uint32_t first_cap, uint32_t lane) {
     if (X.n == 0 || Y.n == 0) return false;
     VCursor cx = cursor_at(X);
-    const uint64_t yb0 = Y.L.boff[Y.obj], yb1 = Y.L.boff[Y.obj + 1];
-    const uint64_t yblk = Y.L.blk[Y.obj];
-    const uint32_t ynblk = uint32_t(Y.L.blk[Y.obj + 1] - yblk);
     uint32_t cap = first_cap;   // a short first tile: a join that ends early decodes less of X
     while (cx.g < cx.nvals) {
         // fill the tile window by window (a window completes at most 128
@@ -91,39 +136,7 @@ __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t
             nt += vdecode_window(cx, ts + nt, te + nt, false, lane);
         }
         wave_lds_sync();
-        if (nt) {
-            const uint32_t x_lo = ts[0], x_hi = te[nt - 1];
-            // Y from the last block whose first start is at or before x_lo
-            VCursor cy = vcursor(Y.L.bytes, yb0, yb1, Y.n);
-            if (Y.n > search_min && ynblk > 1) {
-                uint32_t b = first_gt(Y.L.bval + yblk, ynblk, x_lo, lane);
-                b = b ? b - 1 : 0;
-                if (b) cy = vcursor_block(Y.L.bytes, yb0, yb1, Y.n, b, Y.L.bval[yblk + b], Y.L.bpos[yblk + b]);
-            }
-            while (cy.g < cy.nvals) {
-                wave_lds_sync();
-                const uint32_t k = vdecode_window(cy, ys, ye, true, lane);
-                wave_lds_sync();
-                // a window completes at most 128 intervals: lane l tests
-                // intervals l and l + 64, both searches interleaved; one
-                // outside [x_lo, x_hi) cannot meet the tile and is empty
-                const bool v0 = lane < k, v1 = lane + 64 < k;
-                uint32_t s0 = v0 ? ys[lane] : 0u, e0 = v0 ? ye[lane] : 0u;
-                uint32_t s1 = v1 ? ys[lane + 64] : 0u, e1 = v1 ? ye[lane + 64] : 0u;
-                if (e0 <= x_lo || s0 >= x_hi) e0 = s0 = 0;
-                if (e1 <= x_lo || s1 >= x_hi) e1 = s1 = 0;
-                uint32_t p0 = 0, p1 = 0;
-                for (uint32_t step = 1u << (31 - __builtin_clz(nt)); step; step >>= 1) {
-                    const uint32_t q0 = p0 + step, q1 = p1 + step;
-                    if (q0 <= nt && te[q0 - 1] <= s0) p0 = q0;
-                    if (q1 <= nt && te[q1 - 1] <= s1) p1 = q1;
-                }
-                const bool hit = (p0 < nt && ts[p0] < e0) || (p1 < nt && ts[p1] < e1);
-                if (__any(hit)) return true;
-                // every later Y interval starts after this tile ends
-                if (k == 0 || ys[k - 1] >= x_hi) break;
-            }
-        }
+        if (nt && probe_tile(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
         cap = TILE;
         // a start decoded after the tile's last full interval opens the next tile
         if (cx.g & 1u) {
@@ -135,6 +148,36 @@ __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t
     return false;
 }
 
+// The same join with X already decoded: nx intervals xs/xe in global memory
+// (the wave's decode cache), copied into LDS a tile at a time.
+template <int TILE>
+__device__ bool rjoin(const uint32_t *xs, const uint32_t *xe, uint32_t nx, const ListRef &Y, uint32_t *ts,
+                      uint32_t *te, uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
+    if (nx == 0 || Y.n == 0) return false;
+    for (uint32_t t0 = 0; t0 < nx; t0 += TILE) {
+        const uint32_t nt = min(uint32_t(TILE), nx - t0);
+        wave_lds_sync();
+        for (uint32_t i = lane; i < nt; i += 64) {
+            ts[i] = xs[t0 + i];
+            te[i] = xe[t0 + i];
+        }
+        wave_lds_sync();
+        if (probe_tile(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
+    }
+    return false;
+}
+
+// Decode a whole list into xs/xe (global memory, room for X.n intervals).
+__device__ __forceinline__ void decode_all(const ListRef &X, uint32_t *xs, uint32_t *xe, uint32_t lane) {
+    if (X.n == 0) return;
+    VCursor c = cursor_at(X);
+    while (c.g < c.nvals) {
+        const uint32_t got = vdecode_window(c, xs, xe, false, lane);
+        xs += got;
+        xe += got;
+    }
+}
+
 template <int TILE>
 __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
     __shared__ uint32_t lds[kWavesPerBlock][2 * TILE + 2 * 132];
@@ -142,6 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
     const uint32_t w = uniform(threadIdx.x >> 6);
     uint32_t *ts = lds[w], *te = ts + TILE, *ys = te + TILE, *ye = ys + 132;
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
+    // this wave's decode cache: R's A-list (cas, cae) and F-list (cfs, cfe)
+    const uint32_t cap = a.cache ? a.cache_cap : 0u;
+    uint32_t *cas = a.cache + uint64_t(blockIdx.x * kWavesPerBlock + w) * 4 * cap;
+    uint32_t *cae = cas + cap, *cfs = cae + cap, *cfe = cfs + cap;
+    uint32_t cached = 0xffffffffu;   // the R object held there
     const uint32_t my_xcd = blockIdx.x % a.xcds;
     for (uint32_t k = 0; k < a.xcds; k++) {
         const uint32_t seg = (my_xcd + k) % a.xcds;
@@ -164,12 +212,35 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                 const uint32_t nfr = uint32_t(a.Fr.off[r + 1] - a.Fr.off[r]);
                 const uint32_t nas = uint32_t(a.As.off[s + 1] - a.As.off[s]);
                 const uint32_t nfs = uint32_t(a.Fs.off[s + 1] - a.Fs.off[s]);
+                uint8_t v;
+                if (max(nar, nfr) <= cap) {
+                    // R from the decode cache (decoded once while consecutive
+                    // pairs share it), S streamed
+                    if (r != cached) {
+                        decode_all(ListRef{a.Ar, r, nar}, cas, cae, lane);
+                        decode_all(ListRef{a.Fr, r, nfr}, cfs, cfe, lane);
+                        __threadfence_block();   // the wave's stores, visible to all its lanes
+                        cached = r;
+                    }
+                    const ListRef SA{a.As, s, nas}, SF{a.Fs, s, nfs};
+                    if (!rjoin<TILE>(cas, cae, nar, SA, ts, te, ys, ye, a.search_min, lane)) v = APRIL_TN;
+                    else if (rjoin<TILE>(cas, cae, nar, SF, ts, te, ys, ye, a.search_min, lane) ||
+                             rjoin<TILE>(cfs, cfe, nfr, SA, ts, te, ys, ye, a.search_min, lane))
+                        v = APRIL_TH;
+                    else v = APRIL_INDECISIVE;
+                    if (lane == 0) {
+                        a.verdict[p] = v;
+                        c_tn += v == APRIL_TN;
+                        c_th += v == APRIL_TH;
+                        c_ind += v == APRIL_INDECISIVE;
+                    }
+                    continue;
+                }
                 const bool xs = max(nas, nfs) < max(nar, nfr);
                 const ListRef XA{xs ? a.As : a.Ar, xs ? s : r, xs ? nas : nar};
                 const ListRef XF{xs ? a.Fs : a.Fr, xs ? s : r, xs ? nfs : nfr};
                 const ListRef YA{xs ? a.Ar : a.As, xs ? r : s, xs ? nar : nas};
                 const ListRef YF{xs ? a.Fr : a.Fs, xs ? r : s, xs ? nfr : nfs};
-                uint8_t v;
                 if (!cjoin<TILE>(XA, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane)) v = APRIL_TN;
                 else if (cjoin<TILE>(XA, YF, ts, te, ys, ye, a.search_min, a.first_cap, lane) ||
                          cjoin<TILE>(XF, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane))
@@ -224,6 +295,10 @@ CList clist(const april_lists_t *L, bool f) {
 
 uint64_t vbyte_workspace_bytes() { return kCtrBytes; }
 
+// Intervals per list in a wave's decode cache (R objects with longer lists
+// decode per pair): 4 lists x 4 B x 4096 = 64 KiB per wave.
+constexpr uint32_t kCacheCap = 4096;
+
 int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
                         uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
                         const april_filter_opts_t &o, int cus, void *workspace, hipStream_t stream) {
@@ -241,7 +316,10 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
     a.counts = counts;
     a.xhead = static_cast<unsigned int *>(workspace);
     a.xcds = uint32_t(xcd_count(cus));
-    a.search_min = o.search_min ? o.search_min : 1024;
+    // S is searched from its block index for each tile of R whenever it
+    // spans more than one block (R's tiles come from the decode cache, so S
+    // may be the shorter side)
+    a.search_min = o.search_min ? o.search_min : 64;
     k_zero_ctrs<<<1, 64, 0, stream>>>(a.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     const uint32_t tile = o.tile ? o.tile : 512;
@@ -250,13 +328,27 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
     // (one by default: most joins of overlapping objects end within it)
     a.first_cap = std::min<uint32_t>(tile, 130u * (o.chunk ? o.chunk : 1u));
     const uint64_t blocks = uint64_t(cus) * 8;
+    // decode cache: cache_cap intervals per list for every wave of the grid,
+    // stream-ordered; without one (allocation refused) every pair decodes
+    // both objects
+    a.cache_cap = kCacheCap;
+    a.cache = nullptr;
+    const uint64_t cache_bytes = blocks * kWavesPerBlock * 4ull * kCacheCap * sizeof(uint32_t);
+    if (hipMallocAsync(reinterpret_cast<void **>(&a.cache), cache_bytes, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        a.cache = nullptr;
+    }
     switch (tile) {
         case 256: k_filter_vbyte<256><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
         case 512: k_filter_vbyte<512><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
         case 1024: k_filter_vbyte<1024><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
-        default: return fail(APRIL_E_INVALID, "compressed lists: tile must be 256, 512 or 1024");
+        default:
+            if (a.cache) (void)hipFreeAsync(a.cache, stream);
+            return fail(APRIL_E_INVALID, "compressed lists: tile must be 256, 512 or 1024");
     }
-    APRIL_HIP_TRY(hipGetLastError());
+    const hipError_t e = hipGetLastError();
+    if (a.cache) APRIL_HIP_TRY(hipFreeAsync(a.cache, stream));
+    if (e != hipSuccess) return fail(APRIL_E_HIP, std::string("compressed filter launch: ") + hipGetErrorString(e));
     if (counts) {
         k_sum_totals<<<1, 64, 0, stream>>>(a.xhead, counts, 3);
         APRIL_HIP_TRY(hipGetLastError());

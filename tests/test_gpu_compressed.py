@@ -96,6 +96,13 @@ def test_random_lists_compressed(tile, search_min, chunk):
     assert np.array_equal(v.cpu().numpy(), want)
     assert np.array_equal(c.cpu().numpy(), np.bincount(want, minlength=3))
     assert len(set(want.tolist())) == 3
+    # pairs grouped by R object: runs of pairs share a decoded R list
+    # (objects of up to 4,096 intervals) or decode it per pair (longer ones)
+    o = np.argsort(r, kind="stable")
+    april.april_filter_pairs(dR, dS, cuda(r[o]), cuda(s[o]), v, c, schedule=april.SCHED_BATCHED, tile=tile,
+                             search_min=search_min, chunk=chunk)
+    torch.cuda.synchronize()
+    assert np.array_equal(v.cpu().numpy(), want[o])
 
 
 def test_tiny_workload_compressed():

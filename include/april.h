@@ -426,8 +426,10 @@ typedef struct april_cells april_cells_t;
 int april_build_cells(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off,
                       uint64_t n_lines, uint32_t flags, april_cells_t **out);
 
-/* Upload host cells (read until the stream passes the copies); free both
- * with april_cells_free. */
+/* Upload host cells; free both with april_cells_free.  The device copy holds
+ * each list as maximal runs of consecutive ids, [start, end), which the
+ * polygon-linestring join streams like an A-list (a run meets an interval
+ * exactly when one of its cells does).  Device cells cannot be exported. */
 int april_cells_to_device(const april_cells_t *host, void *hip_stream, april_cells_t **out);
 /* Counts of linestrings and of cell ids. */
 int april_cells_info(const april_cells_t *cells, uint64_t *n_lines, uint64_t *n_ids);

@@ -194,12 +194,11 @@ __device__ __forceinline__ void load_resident(const Resident &x, const uint32_t 
 // FA, each element that overlaps the A-list is also tested against the
 // resident F-list, and an overlap there sets *th and ends the scan.
 //
-// MAP says how a streamed element is read: kAsIs; kShifted, the finer
+// MAP says how a streamed element is read: kAsIs; or kShifted, the finer
 // side's A-interval mapped to the resident (coarser) grid as [s >> sh,
 // ((e - 1) >> sh) + 1), mapped elements staying sorted by start and by end
-// (they may touch or overlap each other), which is all the scan needs; or
-// kUnitCells, a cell id c taken as [c, c + 1) (ye is not read).
-constexpr int kAsIs = 0, kShifted = 1, kUnitCells = 2;
+// (they may touch or overlap each other), which is all the scan needs.
+constexpr int kAsIs = 0, kShifted = 1;
 template <int TILE, int C, bool FA, int MAP>
 __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *__restrict__ ys,
                                              const uint32_t *__restrict__ ye, uint32_t j, uint32_t m,
@@ -212,11 +211,7 @@ __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *
             // lanes past the end load nothing and take an empty [0, 0)
             const uint32_t k = j + c * 64 + lane;
             s[c] = k < m ? gload(ys, k) : 0u;
-            if (MAP == kUnitCells) {
-                e[c] = k < m ? s[c] + 1 : 0u;
-            } else {
-                e[c] = k < m ? gload(ye, k) : 0u;
-            }
+            e[c] = k < m ? gload(ye, k) : 0u;
             if (MAP == kShifted) {
                 s[c] >>= sh;
                 e[c] = k < m ? ((e[c] - 1) >> sh) + 1 : 0u;
@@ -295,8 +290,8 @@ struct PairLists {
 //
 // kMixedOrders: Y is the finer side's A-list mapped to X's grid (shift sh),
 // and only the coarse side's F decides a true hit (Sec. 5.3): no AF pass.
-// kLinestrings: X is the polygon, Y the linestring's cell ids as unit
-// intervals; the first pass decides (a cell inside F(p): a true hit).
+// kLinestrings: X is the polygon, Y the linestring's cells as runs of
+// consecutive ids; the first pass decides (a cell inside F(p): a true hit).
 // kWithinJoin: X is s, Y is A(r); bit 0 of the result is an AA overlap in
 // this piece, bit 1 that every element of A(r) meeting [k0, k1) lies inside
 // one F(s) interval; `want` says which of the two to find (a piece answers
@@ -304,17 +299,15 @@ struct PairLists {
 template <int TILE, int C, int MODE>
 __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLists &L, uint32_t k0, uint32_t k1,
                                                uint32_t search_min, uint32_t lane, uint32_t sh, uint32_t want) {
-    constexpr int MAP = MODE == kMixedOrders ? kShifted : MODE == kLinestrings ? kUnitCells : kAsIs;
+    constexpr int MAP = MODE == kMixedOrders ? kShifted : kAsIs;
     // Y elements that can meet this piece: end above x_lo, start below x_hi
     const uint32_t x_lo = max(k0, uniform(res.as[0]));
     const uint32_t x_hi = min(k1, uniform(res.ae[res.na - 1]));
     const bool narrow = k0 > 0;
     bool th = false;
     // a mapped end ((e - 1) >> sh) + 1 is above x_lo iff e is above x_lo << sh
-    // (a unit cell c ends above x_lo iff c >= x_lo, i.e. c > x_lo - 1)
-    const uint32_t ja = !(narrow || L.nya > search_min) || (MAP == kUnitCells && x_lo == 0) ? 0
-                        : MAP == kUnitCells ? uniform(wave_first_above(L.yas, L.nya, x_lo - 1, lane))
-                                            : uniform(wave_first_above(L.yae, L.nya, MAP == kShifted ? x_lo << sh : x_lo, lane));
+    const uint32_t ja =
+        (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, MAP == kShifted ? x_lo << sh : x_lo, lane)) : 0;
     if (MODE == kWithinJoin) {
         const bool aa = (want & 1) && stream_piece<TILE, C, false, kAsIs>(res, L.yas, L.yae, ja, L.nya, x_hi, lane,
                                                                           &th, 0);

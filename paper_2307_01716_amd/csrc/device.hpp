@@ -119,8 +119,8 @@ int launch_batched_mixed(const FilterArgs &a, uint32_t shift_r, uint32_t shift_s
 // streamed for AA, then tested for lying inside F(s).
 int launch_batched_within(const FilterArgs &a, int cus, void *workspace, hipStream_t stream);
 // The batched schedule for polygon-linestring joins (Sec. 4.3.3): R are the
-// polygons (resident), S the linestrings, As.off / As.s their cell-id lists
-// (As.e and the F views are not read).
+// polygons (resident), S the linestrings, As their cell ids as runs of
+// consecutive ids [start, end) (the F views are not read).
 int launch_batched_linestrings(const FilterArgs &a, int cus, void *workspace, hipStream_t stream);
 
 }  // namespace april

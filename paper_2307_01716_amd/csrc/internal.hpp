@@ -76,10 +76,16 @@ struct april_cells {
     april_grid_t grid{};
     uint64_t n = 0, n_ids = 0;
     int device = -1;                 // -1: host
-    std::vector<uint64_t> off;       // host copy
+    std::vector<uint64_t> off;       // host cells: CSR offsets and sorted ids
     std::vector<uint32_t> ids;
-    uint64_t *d_off = nullptr;       // device copy (one allocation)
-    uint32_t *d_ids = nullptr;
+    // device cells: each list's ids as maximal runs of consecutive ids,
+    // [start, end) (run CSR offsets, starts, ends; one allocation; the host
+    // vectors run_off / ids / run_end hold what was uploaded until the free)
+    std::vector<uint64_t> run_off;
+    std::vector<uint32_t> run_end;
+    uint64_t n_runs = 0;
+    uint64_t *d_off = nullptr;
+    uint32_t *d_ids = nullptr, *d_end = nullptr;
     void *d_block = nullptr;
 };
 

@@ -3,7 +3,8 @@
 //   within joins (Sec. 4.3.2): AA, then every A(r) interval inside one F(s)
 //     interval;
 //   polygon-linestring joins (Sec. 4.3.3): A(p) and F(p) against the
-//     linestring's cell ids taken as intervals [c, c+1);
+//     linestring's cell ids taken as intervals [c, c+1), consecutive ids
+//     merged into one run;
 //   different granularity (Sec. 5.3): the finer side's A mapped to the
 //     coarser grid, a' = [a_s >> n, ((a_e - 1) >> n) + 1), then AA and the
 //     coarser side's F only.
@@ -79,9 +80,9 @@ extern "C" int april_filter_linestrings(const april_lists_t *P, const april_cell
     if (!same_grid(P->grid, L->grid) || P->partition_key != 0)
         return fail(APRIL_E_GRID, "polygons and linestrings use different grids");
     if (n_pairs && (!d_p || !d_l || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
-    // R: the polygons; S: the linestrings, their cell ids in the A view
+    // R: the polygons; S: the linestrings, their runs of cell ids in the A view
     FilterArgs fa = make_args(P, P, d_p, d_l, n_pairs, d_verdict, reinterpret_cast<unsigned long long *>(d_counts));
-    fa.As = {L->d_off, L->d_ids, L->d_ids};
+    fa.As = {L->d_off, L->d_ids, L->d_end};
     fa.Fs = fa.As;
     fa.n_s = L->n;
     return run_batched(fa, P->device, Variant::kLinestrings, 0, 0, static_cast<hipStream_t>(hip_stream));

@@ -148,20 +148,30 @@ __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t
     return false;
 }
 
+// Which tile of the cached R object the LDS tile holds: (first interval << 1)
+// | list (0: A, 1: F), or kNoTile.
+constexpr uint32_t kNoTile = 0xffffffffu;
+
 // The same join with X already decoded: nx intervals xs/xe in global memory
-// (the wave's decode cache), copied into LDS a tile at a time.
+// (the wave's decode cache, list `list` of the cached R object), copied into
+// LDS a tile at a time unless the LDS tile already holds that tile (*held).
 template <int TILE>
-__device__ bool rjoin(const uint32_t *xs, const uint32_t *xe, uint32_t nx, const ListRef &Y, uint32_t *ts,
-                      uint32_t *te, uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
+__device__ bool rjoin(const uint32_t *xs, const uint32_t *xe, uint32_t nx, uint32_t list, uint32_t *held,
+                      const ListRef &Y, uint32_t *ts, uint32_t *te, uint32_t *ys, uint32_t *ye,
+                      uint32_t search_min, uint32_t lane) {
     if (nx == 0 || Y.n == 0) return false;
     for (uint32_t t0 = 0; t0 < nx; t0 += TILE) {
         const uint32_t nt = min(uint32_t(TILE), nx - t0);
-        wave_lds_sync();
-        for (uint32_t i = lane; i < nt; i += 64) {
-            ts[i] = xs[t0 + i];
-            te[i] = xe[t0 + i];
+        const uint32_t key = (t0 << 1) | list;
+        if (*held != key) {
+            wave_lds_sync();
+            for (uint32_t i = lane; i < nt; i += 64) {
+                ts[i] = xs[t0 + i];
+                te[i] = xe[t0 + i];
+            }
+            wave_lds_sync();
+            *held = key;
         }
-        wave_lds_sync();
         if (probe_tile(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
     }
     return false;
@@ -190,6 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
     uint32_t *cas = a.cache + uint64_t(blockIdx.x * kWavesPerBlock + w) * 4 * cap;
     uint32_t *cae = cas + cap, *cfs = cae + cap, *cfe = cfs + cap;
     uint32_t cached = 0xffffffffu;   // the R object held there
+    uint32_t held = kNoTile;         // its tile in ts/te
     const uint32_t my_xcd = blockIdx.x % a.xcds;
     for (uint32_t k = 0; k < a.xcds; k++) {
         const uint32_t seg = (my_xcd + k) % a.xcds;
@@ -221,11 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                         decode_all(ListRef{a.Fr, r, nfr}, cfs, cfe, lane);
                         __threadfence_block();   // the wave's stores, visible to all its lanes
                         cached = r;
+                        held = kNoTile;
                     }
                     const ListRef SA{a.As, s, nas}, SF{a.Fs, s, nfs};
-                    if (!rjoin<TILE>(cas, cae, nar, SA, ts, te, ys, ye, a.search_min, lane)) v = APRIL_TN;
-                    else if (rjoin<TILE>(cas, cae, nar, SF, ts, te, ys, ye, a.search_min, lane) ||
-                             rjoin<TILE>(cfs, cfe, nfr, SA, ts, te, ys, ye, a.search_min, lane))
+                    if (!rjoin<TILE>(cas, cae, nar, 0, &held, SA, ts, te, ys, ye, a.search_min, lane))
+                        v = APRIL_TN;
+                    else if (rjoin<TILE>(cas, cae, nar, 0, &held, SF, ts, te, ys, ye, a.search_min, lane) ||
+                             rjoin<TILE>(cfs, cfe, nfr, 1, &held, SA, ts, te, ys, ye, a.search_min, lane))
                         v = APRIL_TH;
                     else v = APRIL_INDECISIVE;
                     if (lane == 0) {
@@ -241,6 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                 const ListRef XF{xs ? a.Fs : a.Fr, xs ? s : r, xs ? nfs : nfr};
                 const ListRef YA{xs ? a.Ar : a.As, xs ? r : s, xs ? nar : nas};
                 const ListRef YF{xs ? a.Fr : a.Fs, xs ? r : s, xs ? nfr : nfs};
+                held = kNoTile;   // the decoding joins overwrite ts/te
                 if (!cjoin<TILE>(XA, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane)) v = APRIL_TN;
                 else if (cjoin<TILE>(XA, YF, ts, te, ys, ye, a.search_min, a.first_cap, lane) ||
                          cjoin<TILE>(XF, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane))

@@ -3,14 +3,16 @@
 //
 // One wavefront per pair, pairs taken 64 at a time from per-XCD contiguous
 // ranges like the raw batched schedule.  The three joins of Alg. 2 run in
-// order, X being the side with the shorter lists and Y the other:
-// X.A x Y.A, then X.A x Y.F and X.F x Y.A (AF and FA in r/s terms).  A join
-// decodes X tile by tile into LDS (up to TILE intervals); for each tile the
-// Y intervals that can meet it -- from the last block whose first start is at
-// or before the tile's first start, until a Y start reaches the tile's end --
-// are decoded window by window into a small LDS buffer and every lane
-// binary-searches the tile for its Y interval (the overlap test of the raw
-// batched kernel).  A ballot after each window ends the join early.
+// order: X.A x Y.A, then X.A x Y.F and X.F x Y.A.  X is the R object when its
+// lists fit the wave's decode cache: it is decoded once, into the cache, for
+// a run of pairs that share it, and each join copies its tiles from there
+// into LDS (skipping the copy when LDS already holds that tile).  Otherwise X
+// is the side with the shorter lists, decoded tile by tile into LDS by each
+// join.  For each tile, the Y intervals that can meet it are decoded window by
+// window into a small LDS buffer: from the last block whose first start is at
+// or before the tile's first start, until a Y start reaches the tile's end.
+// Every lane binary-searches the tile for its Y intervals (the overlap test of
+// the raw batched kernel).  A ballot after each window ends the join early.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

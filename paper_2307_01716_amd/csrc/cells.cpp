@@ -26,19 +26,19 @@ extern "C" int april_cells_to_device(const april_cells_t *h, void *hip_stream, a
         for (uint64_t k = 0; k < h->n; k++) {
             for (uint64_t t = h->off[k]; t < h->off[k + 1]; t++) {
                 if (t == h->off[k] || h->ids[t] != h->ids[t - 1] + 1) {
-                    C->ids.push_back(h->ids[t]);
+                    C->run_start.push_back(h->ids[t]);
                     C->run_end.push_back(h->ids[t] + 1);
                 } else {
                     C->run_end.back() = h->ids[t] + 1;
                 }
             }
-            C->run_off[k + 1] = C->ids.size();
+            C->run_off[k + 1] = C->run_start.size();
         }
     } catch (const std::bad_alloc &) {
         delete C;
         return fail(APRIL_E_NOMEM, "out of host memory");
     }
-    C->n_runs = C->ids.size();
+    C->n_runs = C->run_start.size();
     const size_t b_off = (8 * (h->n + 1) + 255) & ~size_t(255);
     const size_t b_run = (4 * std::max<uint64_t>(C->n_runs, 1) + 255) & ~size_t(255);
     if (hipGetDevice(&C->device) != hipSuccess || hipMalloc(&C->d_block, b_off + 2 * b_run) != hipSuccess) {
@@ -46,12 +46,12 @@ extern "C" int april_cells_to_device(const april_cells_t *h, void *hip_stream, a
         return fail(APRIL_E_NOMEM, "device allocation of the cells failed");
     }
     C->d_off = static_cast<uint64_t *>(C->d_block);
-    C->d_ids = reinterpret_cast<uint32_t *>(static_cast<char *>(C->d_block) + b_off);
+    C->d_start = reinterpret_cast<uint32_t *>(static_cast<char *>(C->d_block) + b_off);
     C->d_end = reinterpret_cast<uint32_t *>(static_cast<char *>(C->d_block) + b_off + b_run);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     hipError_t e = hipMemcpyAsync(C->d_off, C->run_off.data(), 8 * (h->n + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && C->n_runs)
-        e = hipMemcpyAsync(C->d_ids, C->ids.data(), 4 * C->n_runs, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(C->d_start, C->run_start.data(), 4 * C->n_runs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && C->n_runs)
         e = hipMemcpyAsync(C->d_end, C->run_end.data(), 4 * C->n_runs, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {

@@ -80,12 +80,12 @@ struct april_cells {
     std::vector<uint32_t> ids;
     // device cells: each list's ids as maximal runs of consecutive ids,
     // [start, end) (run CSR offsets, starts, ends; one allocation; the host
-    // vectors run_off / ids / run_end hold what was uploaded until the free)
+    // vectors run_* hold what was uploaded until the free)
     std::vector<uint64_t> run_off;
-    std::vector<uint32_t> run_end;
+    std::vector<uint32_t> run_start, run_end;
     uint64_t n_runs = 0;
     uint64_t *d_off = nullptr;
-    uint32_t *d_ids = nullptr, *d_end = nullptr;
+    uint32_t *d_start = nullptr, *d_end = nullptr;
     void *d_block = nullptr;
 };
 

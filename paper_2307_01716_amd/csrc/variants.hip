@@ -82,7 +82,7 @@ extern "C" int april_filter_linestrings(const april_lists_t *P, const april_cell
     if (n_pairs && (!d_p || !d_l || !d_verdict)) return fail(APRIL_E_INVALID, "NULL pair/verdict array");
     // R: the polygons; S: the linestrings, their runs of cell ids in the A view
     FilterArgs fa = make_args(P, P, d_p, d_l, n_pairs, d_verdict, reinterpret_cast<unsigned long long *>(d_counts));
-    fa.As = {L->d_off, L->d_ids, L->d_end};
+    fa.As = {L->d_off, L->d_start, L->d_end};
     fa.Fs = fa.As;
     fa.n_s = L->n;
     return run_batched(fa, P->device, Variant::kLinestrings, 0, 0, static_cast<hipStream_t>(hip_stream));

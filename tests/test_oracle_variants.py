@@ -244,3 +244,26 @@ def test_mixed_sound_on_tiny():
         hit = oracle.polygons_intersect(R.polygon(int(r[p])), S.polygon(int(s[p])))
         assert hit == (v[p] == TH), p
     assert (v == TH).sum() > 0 and (v == TN).sum() > 0
+
+
+def test_linestring_runs_give_the_cell_verdicts():
+    """The GPU path streams a linestring's cells as maximal runs of
+    consecutive ids.  A run [c0, c1 + 1) meets an interval exactly when one of
+    its cells [c, c + 1) does, so Alg. 2's joins on the runs must give the
+    oracle's cell-by-cell verdicts (Sec. 4.3.3) -- checked here with the
+    oracle's own interval join on every candidate pair of a small workload."""
+    P, L, g = synth.configs.linestring_scale(n_poly=1500, n_lines=1500)
+    LP, CL = oracle.build_lists(g, P), oracle.build_cells(g, L)
+    p, l = oracle.mbr_join(P, L)
+    want = oracle.filter_linestrings(LP, CL, p, l)
+    run_lists = [runs(CL.cells(k)) for k in range(len(CL))]
+    shorter = sum(len(s) for s, _ in run_lists) < len(CL.ids)
+    got = []
+    for a, b in zip(p, l):
+        rs = run_lists[b]
+        if not oracle.interval_join(LP.A(a), rs)[0]:
+            got.append(TN)
+        else:
+            got.append(TH if oracle.interval_join(LP.F(a), rs)[0] else IND)
+    assert np.array_equal(np.array(got, np.uint8), want)
+    assert set(np.unique(want)) == {TN, TH, IND} and shorter

@@ -216,10 +216,13 @@ int april_lists_load(const char *path, int validate, april_lists_t **out);
 #define APRIL_SCHED_BATCHED 1u  /* length-binned persistent schedule */
 
 #define APRIL_VALIDATE 1u       /* check indices first; synchronous; APRIL_E_INVALID */
+#define APRIL_WS_DECODE_CACHE 2u /* compressed lists: the workspace also holds the decode
+                                    cache (april_filter_workspace_size counts it when this
+                                    flag is set), so the call allocates nothing */
 
 typedef struct {
     uint32_t schedule;     /* APRIL_SCHED_* */
-    uint32_t flags;        /* APRIL_VALIDATE */
+    uint32_t flags;        /* APRIL_VALIDATE | APRIL_WS_DECODE_CACHE */
     uint32_t waves;        /* resident wavefronts (0 = library default) */
     uint32_t tile;         /* batched: intervals per list kept in LDS per wavefront:
                               128, 256 or 512 (0 = 256 when the two collections' A-lists
@@ -244,7 +247,9 @@ typedef struct {
 /*
  * Device scratch a filter call may use: the batched schedule's work
  * counters and, for any schedule, the slots that sum d_counts (16 KiB,
- * whatever n_pairs and the schedule).
+ * whatever n_pairs and the schedule); with APRIL_WS_DECODE_CACHE in
+ * opts->flags, plus the compressed filter's decode cache on the current
+ * device.
  */
 int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opts, uint64_t *bytes);
 
@@ -264,13 +269,15 @@ int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opt
  *                        pair.  Launches only kernels when a workspace is
  *                        passed, so it can be captured in a hipGraph.
  *                        Compressed lists (APRIL_CODEC_VBYTE) run one
- *                        wavefront per pair decoding as it joins; the call
- *                        also takes a stream-ordered decode cache (64 KiB
- *                        per wavefront, 512 MiB on 256 CUs) that keeps R
- *                        objects of up to 4,096 intervals per list decoded
- *                        while consecutive pairs share them (without it,
- *                        when the allocation is refused, every pair decodes
- *                        both objects; the verdicts are the same).
+ *                        wavefront per pair decoding as it joins, with a
+ *                        decode cache (64 KiB per wavefront, 512 MiB on 256
+ *                        CUs) that keeps R objects of up to 4,096 intervals
+ *                        per list decoded while consecutive pairs share
+ *                        them.  With APRIL_WS_DECODE_CACHE the cache is the
+ *                        workspace's tail; else the call takes it from the
+ *                        stream (stream-ordered), and when that allocation is
+ *                        refused every pair decodes both objects (the
+ *                        verdicts are the same).
  *   R, S        device-resident lists on the same grid (else APRIL_E_GRID)
  *   d_r, d_s    device uint32[n_pairs]: pair p is (R object d_r[p], S object d_s[p])
  *   d_verdict   device uint8[n_pairs]: APRIL_TN / APRIL_TH / APRIL_INDECISIVE,

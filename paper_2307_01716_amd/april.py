@@ -25,6 +25,7 @@ GRID_PARTITIONED = 1
 CODEC_RAW, CODEC_VBYTE = 0, 1
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 VALIDATE = 1
+WS_DECODE_CACHE = 2
 
 _ERRNAMES = {E_INVALID: "APRIL_E_INVALID", E_GRID: "APRIL_E_GRID", E_NOMEM: "APRIL_E_NOMEM",
              E_HIP: "APRIL_E_HIP", E_CORRUPT: "APRIL_E_CORRUPT", E_NODEV: "APRIL_E_NODEV",
@@ -285,8 +286,8 @@ def _opts(schedule=SCHED_PLAIN, flags=0, waves=0, tile=0, chunk=0, thread_max=0,
                                0, ws, nbytes)
 
 
-def april_filter_workspace_size(n_pairs: int, schedule=SCHED_BATCHED) -> int:
-    o = _opts(schedule)
+def april_filter_workspace_size(n_pairs: int, schedule=SCHED_BATCHED, flags=0) -> int:
+    o = _opts(schedule, flags)
     out = C.c_uint64()
     _check(lib().april_filter_workspace_size(n_pairs, C.byref(o), C.byref(out)))
     return out.value

@@ -314,6 +314,15 @@ uint64_t vbyte_workspace_bytes() { return kCtrBytes; }
 // Intervals per list in a wave's decode cache (R objects with longer lists
 // decode per pair): 4 lists x 4 B x 4096 = 64 KiB per wave.
 constexpr uint32_t kCacheCap = 4096;
+// Blocks of the compressed filter's grid per CU.
+constexpr uint64_t kVbyteBlocksPerCu = 8;
+
+uint64_t vbyte_cache_bytes(int cus) {
+    return uint64_t(cus) * kVbyteBlocksPerCu * kWavesPerBlock * 4ull * kCacheCap * sizeof(uint32_t);
+}
+
+// the counters first, the cache 256-byte aligned after them
+uint64_t vbyte_cache_offset() { return (kCtrBytes + 255) & ~uint64_t(255); }
 
 int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
                         uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
@@ -343,14 +352,21 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
     if (o.chunk > 4) return fail(APRIL_E_INVALID, "compressed lists: chunk must be 0 to 4");
     // (one by default: most joins of overlapping objects end within it)
     a.first_cap = std::min<uint32_t>(tile, 130u * (o.chunk ? o.chunk : 1u));
-    const uint64_t blocks = uint64_t(cus) * 8;
+    const uint64_t blocks = uint64_t(cus) * kVbyteBlocksPerCu;
     // decode cache: cache_cap intervals per list for every wave of the grid,
-    // stream-ordered; without one (allocation refused) every pair decodes
-    // both objects
+    // from the caller's workspace (APRIL_WS_DECODE_CACHE) or stream-ordered;
+    // without one (allocation refused) every pair decodes both objects
     a.cache_cap = kCacheCap;
     a.cache = nullptr;
-    const uint64_t cache_bytes = blocks * kWavesPerBlock * 4ull * kCacheCap * sizeof(uint32_t);
-    if (hipMallocAsync(reinterpret_cast<void **>(&a.cache), cache_bytes, stream) != hipSuccess) {
+    const uint64_t cache_bytes = vbyte_cache_bytes(cus);
+    bool own_cache = false;
+    if (o.flags & APRIL_WS_DECODE_CACHE) {
+        if (!o.d_workspace || o.workspace_bytes < vbyte_cache_offset() + cache_bytes)
+            return fail(APRIL_E_INVALID, "workspace too small for the decode cache");
+        a.cache = reinterpret_cast<uint32_t *>(static_cast<char *>(o.d_workspace) + vbyte_cache_offset());
+    } else if (hipMallocAsync(reinterpret_cast<void **>(&a.cache), cache_bytes, stream) == hipSuccess) {
+        own_cache = true;
+    } else {
         (void)hipGetLastError();
         a.cache = nullptr;
     }
@@ -359,11 +375,11 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
         case 512: k_filter_vbyte<512><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
         case 1024: k_filter_vbyte<1024><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(a); break;
         default:
-            if (a.cache) (void)hipFreeAsync(a.cache, stream);
+            if (own_cache) (void)hipFreeAsync(a.cache, stream);
             return fail(APRIL_E_INVALID, "compressed lists: tile must be 256, 512 or 1024");
     }
     const hipError_t e = hipGetLastError();
-    if (a.cache) APRIL_HIP_TRY(hipFreeAsync(a.cache, stream));
+    if (own_cache) APRIL_HIP_TRY(hipFreeAsync(a.cache, stream));
     if (e != hipSuccess) return fail(APRIL_E_HIP, std::string("compressed filter launch: ") + hipGetErrorString(e));
     if (counts) {
         k_sum_totals<<<1, 64, 0, stream>>>(a.xhead, counts, 3);

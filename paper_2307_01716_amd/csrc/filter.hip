@@ -380,5 +380,10 @@ extern "C" int april_filter_workspace_size(uint64_t n_pairs, const april_filter_
     clear_error();
     if (!bytes) return fail(APRIL_E_INVALID, "NULL argument");
     *bytes = batched_workspace_bytes(n_pairs);   // plain: the scratch that sums the counts
+    if (opts && (opts->flags & APRIL_WS_DECODE_CACHE)) {
+        DeviceState *st;
+        if (int rc = device_state(&st)) return rc;
+        *bytes = vbyte_cache_offset() + vbyte_cache_bytes(st->cus);
+    }
     return APRIL_OK;
 }

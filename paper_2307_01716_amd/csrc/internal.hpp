@@ -147,6 +147,10 @@ struct ProbeQuery {
 int launch_decode_lists(const april_lists_t *L, bool f, uint32_t *out_s, uint32_t *out_e, hipStream_t stream);
 // The filter on compressed lists (compressed.hip); `workspace` holds the
 // work counters (kCtrBytes).
+// The compressed filter's decode cache: its size for a device of `cus` CUs,
+// and where it starts in a workspace that holds it.
+uint64_t vbyte_cache_bytes(int cus);
+uint64_t vbyte_cache_offset();
 int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
                         uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
                         const april_filter_opts_t &o, int cus, void *workspace, hipStream_t stream);

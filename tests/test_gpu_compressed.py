@@ -6,7 +6,8 @@
   small gaps (1- to 5-byte varints);
 * verdicts on compressed lists equal the oracle's (random lists, the tiny
   workload), with the block-index search forced on and off and every tile
-  size.
+  size, with pairs in random order and grouped by R object, and with the
+  decode cache in the caller's workspace.
 """
 
 import sys
@@ -103,6 +104,43 @@ def test_random_lists_compressed(tile, search_min, chunk):
                              search_min=search_min, chunk=chunk)
     torch.cuda.synchronize()
     assert np.array_equal(v.cpu().numpy(), want[o])
+
+
+def test_decode_cache_in_workspace():
+    """APRIL_WS_DECODE_CACHE: the decode cache is the tail of the caller's
+    workspace, so the call allocates nothing.  Verdicts equal the oracle's on
+    two calls in a row through the same workspace, the second on fewer pairs
+    (objects above the cache's 4,096 intervals decode per pair); a workspace
+    without room for the cache is refused."""
+    rng = np.random.default_rng(21)
+    n = 120
+    lens = rng.choice([1, 5, 60, 300, 1500, 5000], n)
+    spread = rng.choice([3, 40, 2000], n)
+    LR, LS = collection(rng, lens, spread), collection(rng, lens[::-1].copy(), spread)
+    P = 4000
+    r = np.sort(rng.integers(0, n, P)).astype(np.uint32)
+    s = rng.integers(0, n, P).astype(np.uint32)
+    want = oracle.filter_pairs(LR, LS, r, s)
+    dR, dS = upload(GRID, LR, april.CODEC_VBYTE), upload(GRID, LS, april.CODEC_VBYTE)
+    nb = april.april_filter_workspace_size(P, flags=april.WS_DECODE_CACHE)
+    plain_nb = april.april_filter_workspace_size(P)
+    assert nb > plain_nb
+    say(f"[vbyte] decode cache in a workspace of {nb} bytes")
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    for m in (P, P // 3):
+        v = torch.empty(m, dtype=torch.uint8, device="cuda")
+        c = torch.empty(3, dtype=torch.int64, device="cuda")
+        april.april_filter_pairs(dR, dS, cuda(r[:m]), cuda(s[:m]), v, c, schedule=april.SCHED_BATCHED,
+                                 flags=april.WS_DECODE_CACHE, workspace=ws)
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), want[:m])
+        assert np.array_equal(c.cpu().numpy(), np.bincount(want[:m], minlength=3))
+    v = torch.empty(P, dtype=torch.uint8, device="cuda")
+    with pytest.raises(april.AprilError) as e:
+        april.april_filter_pairs(dR, dS, cuda(r), cuda(s), v, None, schedule=april.SCHED_BATCHED,
+                                 flags=april.WS_DECODE_CACHE, workspace=ws[:plain_nb])
+    assert e.value.code == april.E_INVALID
+    torch.cuda.synchronize()
 
 
 def test_tiny_workload_compressed():

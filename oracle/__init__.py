@@ -66,6 +66,7 @@ def _load():
     L.orc_hilbert.argtypes = [i32, u64, u64]
     L.orc_hilbert_many.argtypes = [i32, P, P, i64, P]
     L.orc_classify.argtypes = [d, d, d, i32, P, i64, C.POINTER(P), C.POINTER(i64)]
+    L.orc_classify_cells.argtypes = [d, d, d, i32, P, i64, P, i64, P]
     L.orc_free.argtypes = [P]
     L.orc_build.argtypes = [d, d, d, i32, P, P, i64, i32, C.POINTER(P)]
     L.orc_lists_sizes.argtypes = [P, C.POINTER(i64), C.POINTER(i64)]
@@ -136,6 +137,16 @@ def classify(grid, xy: np.ndarray) -> np.ndarray:
         out = np.array(buf, dtype=np.int64).reshape(-1, 3)
     finally:
         L.orc_free(ptr)
+    return out
+
+
+def classify_cells(grid, xy: np.ndarray, ij: np.ndarray) -> np.ndarray:
+    """Classes (0 Empty, 1 Partial, 2 Full) of the given cells, rows of ij =
+    (i, j), each decided by brute force over all of the polygon's edges."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    ij = np.ascontiguousarray(ij, dtype=np.int64).reshape(-1, 2)
+    out = np.empty(len(ij), dtype=np.uint8)
+    _check(_load().orc_classify_cells(*_grid_args(grid), _p(xy), len(xy), _p(ij), len(ij), _p(out)))
     return out
 
 

@@ -114,7 +114,9 @@ def _grid_args(grid):
 
 
 def default_threads() -> int:
-    return max(1, len(os.sched_getaffinity(0)))
+    """Host threads for the oracle's parallel loops: the CPUs this process
+    may run on, at most 16 (a GPU host's share per GPU)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def hilbert(order: int, x, y) -> np.ndarray:
@@ -267,31 +269,55 @@ def twice_area(xy: np.ndarray) -> int:
     return (hi.value << 64) + lo.value
 
 
+def _partition_local_pairs(layout, R, S, p, nthreads):
+    """Partition p's candidate pairs (Sec. 5.2) as local indices (i, j) into
+    its R and S instances: MBR pairs of its instances kept only where the
+    lower-left corner of the two MBRs' intersection lies in p."""
+    k = layout.k
+    ro = layout.r_obj[layout.r_off[p]:layout.r_off[p + 1]]
+    so = layout.s_obj[layout.s_off[p]:layout.s_off[p + 1]]
+    if len(ro) == 0 or len(so) == 0:
+        return ro, so, None, None
+    Rp, Sp = R.subset(ro), S.subset(so)
+    i, j = mbr_join(Rp, Sp, nthreads)
+    br, bs = Rp.mbrs()[i], Sp.mbrs()[j]
+    cx = np.maximum(br[:, 0], bs[:, 0])
+    cy = np.maximum(br[:, 1], bs[:, 1])
+    pi = np.clip(np.floor(cx * k), 0, k - 1).astype(np.int64)
+    pj = np.clip(np.floor(cy * k), 0, k - 1).astype(np.int64)
+    keep = (pj * k + pi) == p
+    return ro, so, i[keep], j[keep]
+
+
+def partitioned_pairs(layout, R, S, nthreads: int = 0):
+    """Partition-local candidate pairs of all partitions as instance indices
+    (R instance layout.r_off[p] + i, S instance layout.s_off[p] + j), sorted."""
+    out_r, out_s = [], []
+    for p in range(layout.k * layout.k):
+        ro, so, i, j = _partition_local_pairs(layout, R, S, p, nthreads)
+        if i is None or len(i) == 0:
+            continue
+        out_r.append(i.astype(np.int64) + int(layout.r_off[p]))
+        out_s.append(j.astype(np.int64) + int(layout.s_off[p]))
+    if not out_r:
+        z = np.zeros(0, np.int64)
+        return z, z
+    r, s = np.concatenate(out_r), np.concatenate(out_s)
+    order = np.lexsort((s, r))
+    return r[order], s[order]
+
+
 def partitioned_filter(layout, R, S, nthreads: int = 0):
     """Partitioned join (Sec. 5.2), partition by partition: lists of each
     partition's instances on its own grid, the partition's MBR pairs kept only
     where the lower-left corner of the MBR intersection lies in it, Alg. 2 on
     them.  Returns (r, s, verdict) with global object ids, sorted by (r, s)."""
     out = []
-    k = layout.k
-    for p in range(k * k):
-        ro = layout.r_obj[layout.r_off[p]:layout.r_off[p + 1]]
-        so = layout.s_obj[layout.s_off[p]:layout.s_off[p + 1]]
-        if len(ro) == 0 or len(so) == 0:
+    for p in range(layout.k * layout.k):
+        ro, so, i, j = _partition_local_pairs(layout, R, S, p, nthreads)
+        if i is None or len(i) == 0:
             continue
         Rp, Sp = R.subset(ro), S.subset(so)
-        i, j = mbr_join(Rp, Sp, nthreads)
-        if len(i) == 0:
-            continue
-        br, bs = Rp.mbrs()[i], Sp.mbrs()[j]
-        cx = np.maximum(br[:, 0], bs[:, 0])
-        cy = np.maximum(br[:, 1], bs[:, 1])
-        pi = np.clip(np.floor(cx * k), 0, k - 1).astype(np.int64)
-        pj = np.clip(np.floor(cy * k), 0, k - 1).astype(np.int64)
-        keep = (pj * k + pi) == p
-        i, j = i[keep], j[keep]
-        if len(i) == 0:
-            continue
         g = layout.grids[p]
         v = filter_pairs(build_lists(g, Rp, nthreads), build_lists(g, Sp, nthreads), i, j, nthreads)
         out.append((ro[i], so[j], v))

@@ -11,6 +11,7 @@
 """
 
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -191,3 +192,56 @@ def test_partitioned_compressed_against_oracle(parts):
     april.april_filter_pairs(dRr, dSr, cuda(r), cuda(s), v2, schedule=april.SCHED_BATCHED)
     torch.cuda.synchronize()
     assert torch.equal(v, v2)
+
+
+def test_partitioned_config_size_against_oracle():
+    """The partitioned workload at its layout: 16 x 16 partitions, each with
+    its own grid of order 16, 100k polygons per side of the at-scale
+    distribution (a fifth of the benchmark's 500k).  The oracle's brute-force
+    builder needs about a second per instance at this resolution, so:
+      * the library's partition-local pairs equal the oracle's (same instance
+        indices, reference-point rule);
+      * the library's lists equal the oracle's on 64 sampled instances per
+        side, each built on its own partition's grid;
+      * Alg. 2 by the oracle on the library's lists, for every pair, equals
+        the GPU verdicts on raw and on compressed lists (one launch each)."""
+    from paper_2307_01716_amd import partitioned
+    R, S, lay = synth.configs.partitioned(n=100_000)
+    say(f"[partitioned-16x16] instances {len(lay.r_obj)} + {len(lay.s_obj)}; host lists")
+    hR = partitioned.build_instances(lay, R, "r")
+    hS = partitioned.build_instances(lay, S, "s")
+    r, s = partitioned.pairs(lay, R, S)
+    ro, so = oracle.partitioned_pairs(lay, R, S)
+    k = np.lexsort((s, r))
+    assert np.array_equal(r[k].astype(np.int64), ro) and np.array_equal(s[k].astype(np.int64), so)
+    LR, LS = oracle.Lists(*hR.export()), oracle.Lists(*hS.export())
+    rng = np.random.default_rng(44)
+    for name, L, P, obj, part in (("r", LR, R, lay.r_obj, lay.r_part()),
+                                  ("s", LS, S, lay.s_obj, lay.s_part())):
+        pick = rng.choice(len(obj), 64, replace=False)
+        say(f"[partitioned-16x16] oracle lists of 64 sampled {name} instances")
+
+        def one(i):
+            return oracle.build_lists(lay.grids[int(part[i])], P.subset(np.array([obj[i]])), nthreads=1)
+        with ThreadPoolExecutor(oracle.default_threads()) as ex:
+            built = list(ex.map(one, pick))
+        for i, want in zip(pick, built):
+            a0, a1 = int(L.offA[i]), int(L.offA[i + 1])
+            f0, f1 = int(L.offF[i]), int(L.offF[i + 1])
+            assert np.array_equal(L.sA[a0:a1], want.sA) and np.array_equal(L.eA[a0:a1], want.eA), i
+            assert np.array_equal(L.sF[f0:f1], want.sF) and np.array_equal(L.eF[f0:f1], want.eF), i
+    say(f"[partitioned-16x16] oracle filter over {len(r)} pairs")
+    want = oracle.filter_pairs(LR, LS, r, s)
+    assert set(np.unique(want)) == {0, 1, 2}
+    for codec in (april.CODEC_RAW, april.CODEC_VBYTE):
+        dR = april.april_lists_to_device(hR, codec=codec)
+        dS = april.april_lists_to_device(hS, codec=codec)
+        v = torch.empty(len(r), dtype=torch.uint8, device="cuda")
+        c = torch.empty(3, dtype=torch.int64, device="cuda")
+        say(f"[partitioned-16x16] batched, codec={codec}")
+        april.april_filter_pairs(dR, dS, cuda(r), cuda(s), v, c, schedule=april.SCHED_BATCHED)
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), want), codec
+        assert np.array_equal(c.cpu().numpy(), np.bincount(want, minlength=3)), codec
+        dR.free()
+        dS.free()

@@ -7,10 +7,10 @@ Cases:
     negative) and the same with one overlap planted near the end;
   * the tiny workload end to end (the library's own lists vs the oracle's,
     verdicts, counts, Alg. 2 byte counts);
-  * the at-scale workload (200k x 200k polygons, ~4.7M pairs) in the launch
-    configuration the benchmark times: every verdict checked against
-    properties that hold at any size, a random sample checked against the
-    oracle one by one;
+  * the at-scale workload (200k x 200k polygons, ~4.7M pairs): the oracle's
+    own lists of all 400k polygons equal the library's, and every verdict of
+    every schedule (also the benchmark's hipGraph launch and compressed
+    lists) equals the oracle's Alg. 2 on its lists;
   * edge cases: no pairs, out-of-range indices, duplicated pairs;
   * lists that went through list files (save, load, upload in both codecs).
 """
@@ -247,57 +247,108 @@ def test_grid_mismatch(tiny):
 def scale():
     say("[scale] generating 200k x 200k")
     R, S, g = synth.configs.scale()
-    r, s = oracle.mbr_join(R, S)
+    r, s = april.april_mbr_join(R.mbrs(), S.mbrs())
     hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
     hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
     dR = april.april_lists_to_device(hR)
     dS = april.april_lists_to_device(hS)
     torch.cuda.synchronize()
-    return R, S, g, r, s, dR, dS
+    return R, S, g, r, s, hR, hS, dR, dS
 
 
 @pytest.fixture(scope="module")
-def scale_plain(scale):
-    R, S, g, r, s, dR, dS = scale
-    say(f"[scale] plain filter over {len(r)} pairs")
-    return gpu_filter(dR, dS, r, s)
+def scale_oracle(scale):
+    """The oracle end to end on the whole at-scale workload: its own lists of
+    all 400k polygons (brute-force classification) and Alg. 2 on every
+    candidate pair."""
+    R, S, g, r, s, hR, hS, dR, dS = scale
+    say("[scale] oracle lists of all 400k polygons")
+    LR = oracle.build_lists(g, R)
+    LS = oracle.build_lists(g, S)
+    say(f"[scale] oracle filter over all {len(r)} pairs")
+    return LR, LS, oracle.filter_pairs(LR, LS, r, s)
 
 
-def test_scale_sampled_against_oracle(scale, scale_plain):
-    R, S, g, r, s, dR, dS = scale
-    got, cnt = scale_plain
-    assert np.array_equal(cnt, np.bincount(got, minlength=3))
-    assert cnt.sum() == len(r)
-    rng = np.random.default_rng(17)
-    pick = np.sort(rng.choice(len(r), 3000, replace=False))
-    ur, ir = np.unique(r[pick], return_inverse=True)
-    us, is_ = np.unique(s[pick], return_inverse=True)
-    say(f"[scale] oracle lists for {len(ur)} + {len(us)} sampled polygons")
-    LR = oracle.build_lists(g, R.subset(ur))
-    LS = oracle.build_lists(g, S.subset(us))
-    want = oracle.filter_pairs(LR, LS, ir.astype(np.uint32), is_.astype(np.uint32))
-    assert np.array_equal(got[pick], want)
-    assert set(np.unique(want)) == {0, 1, 2}
+def test_scale_lists_equal_oracle(scale, scale_oracle):
+    """The library's host lists of every at-scale polygon equal the oracle's."""
+    R, S, g, r, s, hR, hS, dR, dS = scale
+    LR, LS, _ = scale_oracle
+    for h, L in ((hR, LR), (hS, LS)):
+        got = h.export()
+        want = (L.offA, L.sA, L.eA, L.offF, L.sF, L.eF)
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b)
 
 
-def test_scale_swapped_roles(scale):
-    R, S, g, r, s, dR, dS = scale
-    say("[scale] swapped roles")
-    a, _ = gpu_filter(dR, dS, r, s)
-    b, _ = gpu_filter(dS, dR, s, r)
-    assert np.array_equal(a, b)
+def test_scale_pairs_equal_oracle(scale):
+    """The library's MBR join gives the oracle's candidate pairs (as a set)."""
+    R, S, g, r, s, hR, hS, dR, dS = scale
+    ro, so = oracle.mbr_join(R, S)
+    k = np.lexsort((s, r))
+    assert np.array_equal(r[k], ro) and np.array_equal(s[k], so)
 
 
-@pytest.mark.parametrize("sched", ["batched", "batched-small-tiles", "batched-wide"])
-def test_scale_batched_equals_plain(scale, scale_plain, sched):
-    """Full-size check of the batched schedule in the benchmark's launch
-    configuration: every verdict equals the plain kernel's (itself checked
-    against the oracle on a sample above)."""
-    R, S, g, r, s, dR, dS = scale
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+def test_scale_every_pair_against_oracle(scale, scale_oracle, sched):
+    """Every one of the ~4.7M at-scale verdicts, under each schedule, equals
+    the oracle's, and so do the counts; then the same with R and S swapped."""
+    R, S, g, r, s, hR, hS, dR, dS = scale
+    want = scale_oracle[2]
     say(f"[scale] {sched} over {len(r)} pairs")
     got, cnt = gpu_filter(dR, dS, r, s, **SCHEDULES[sched])
-    assert np.array_equal(got, scale_plain[0])
-    assert np.array_equal(cnt, scale_plain[1])
+    assert np.array_equal(got, want)
+    assert np.array_equal(cnt, np.bincount(want, minlength=3))
+    assert set(np.unique(want)) == {0, 1, 2}
+    say(f"[scale] {sched} swapped roles")
+    got2, cnt2 = gpu_filter(dS, dR, s, r, **SCHEDULES[sched])
+    assert np.array_equal(got2, want)
+    assert np.array_equal(cnt2, cnt)
+
+
+def test_scale_graph_launch_against_oracle(scale, scale_oracle):
+    """The benchmark's launch: the batched schedule with library defaults and
+    a caller workspace, captured in a hipGraph and replayed; every replay's
+    verdicts and counts equal the oracle's."""
+    R, S, g, r, s, hR, hS, dR, dS = scale
+    want = scale_oracle[2]
+    P = len(r)
+    ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
+    rt, st = cuda(r), cuda(s)
+    verdict = torch.empty(P, dtype=torch.uint8, device="cuda")
+    counts = torch.empty(3, dtype=torch.int64, device="cuda")
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    say("[scale] graph capture")
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            april.april_filter_pairs(dR, dS, rt, st, verdict, counts, schedule=april.SCHED_BATCHED,
+                                     workspace=ws, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        verdict.fill_(99)
+        counts.fill_(-1)
+        torch.cuda.synchronize()
+        say(f"[scale] graph replay {rep}")
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(verdict.cpu().numpy(), want), rep
+        assert np.array_equal(counts.cpu().numpy(), np.bincount(want, minlength=3)), rep
+
+
+def test_scale_compressed_against_oracle(scale, scale_oracle):
+    """The at-scale lists uploaded delta + VByte: every verdict equals the
+    oracle's."""
+    R, S, g, r, s, hR, hS, dR, dS = scale
+    want = scale_oracle[2]
+    cR = april.april_lists_to_device(hR, codec=april.CODEC_VBYTE)
+    cS = april.april_lists_to_device(hS, codec=april.CODEC_VBYTE)
+    say(f"[scale] compressed over {len(r)} pairs")
+    got, cnt = gpu_filter(cR, cS, r, s, schedule=april.SCHED_BATCHED)
+    assert np.array_equal(got, want)
+    assert np.array_equal(cnt, np.bincount(want, minlength=3))
+    cR.free()
+    cS.free()
 
 
 def test_batched_workspace_and_graph(tiny):

@@ -1,7 +1,9 @@
 """Served selection queries (Sec. 4.3.1): continuous batching on the GPU.
 
-* every result equals, bit for bit, the oracle's answer for that query: the
-  S objects whose closed MBR meets the query's, with Alg. 2's verdicts;
+* with S = 200k polygons and 300 queries of 10-10^4 vertices, every
+  result equals, bit for bit, the oracle's answer for that query: the S
+  objects whose closed MBR meets the query's, with Alg. 2's verdicts on the
+  oracle's own lists;
 * a request's result is the same alone and in a mix of concurrent requests;
 * a request larger than a slot fails with APRIL_E_NOMEM without disturbing
   the others; cancelled requests disappear; unknown tickets are errors;
@@ -11,6 +13,7 @@
 
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -31,8 +34,7 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def served():
-    S, Q, g = synth.configs.serving(n_s=20_000, n_queries=300)
-    # keep the very large queries few: the mixture of sizes still spans 10..10^4
+    S, Q, g = synth.configs.serving(n_s=200_000, n_queries=300)
     say(f"[serve] S={len(S)} queries={len(Q)}")
     hS = april.april_build_lists(g, S.xy, S.voff, april.STRICT)
     dS = april.april_lists_to_device(hS)
@@ -40,13 +42,27 @@ def served():
     return S, Q, g, hS, dS
 
 
-def oracle_answer(S, g, LS, poly):
-    """(s ids ascending, verdicts) for one query, from the oracle alone."""
-    one = synth.PolygonSet(np.ascontiguousarray(poly), np.array([0, len(poly)], np.int64))
-    _, s = oracle.mbr_join(one, S)
-    LQ = oracle.build_lists(g, one)
-    v = oracle.filter_pairs(LQ, LS, np.zeros(len(s), np.uint32), s)
-    return s, v
+def oracle_answers(S, Q, g):
+    """Per query (s ids ascending, verdicts), from the oracle alone: its own
+    lists of S and of every query (brute-force classification, one query
+    per thread), the closed-MBR pairs, Alg. 2 on each pair."""
+    LS = oracle.build_lists(g, S)
+
+    def one(k):
+        poly = np.ascontiguousarray(Q.polygon(k))
+        return oracle.build_lists(g, synth.PolygonSet(poly, np.array([0, len(poly)], np.int64)), nthreads=1)
+    # the largest queries first, so that no thread is left with one at the end
+    mb = Q.mbrs()
+    order = np.argsort(-(mb[:, 2] - mb[:, 0]) * (mb[:, 3] - mb[:, 1]) * np.diff(Q.voff))
+    with ThreadPoolExecutor(oracle.default_threads()) as ex:
+        built = dict(zip(order.tolist(), ex.map(one, order.tolist())))
+    q, s = oracle.mbr_join(Q, S)
+    out = []
+    for k in range(len(Q)):
+        sk = s[q == k]
+        v = oracle.filter_pairs(built[k], LS, np.zeros(len(sk), np.uint32), sk)
+        out.append((sk, v))
+    return out
 
 
 def test_alone_equals_mix_and_oracle(served):
@@ -68,16 +84,17 @@ def test_alone_equals_mix_and_oracle(served):
         for k in range(40):
             assert np.array_equal(alone[k].s_ids, mix[k].s_ids), k
             assert np.array_equal(alone[k].verdict, mix[k].verdict), k
-        say("[serve] oracle on a sample")
-        LS = oracle.build_lists(g, S)
-        rng = np.random.default_rng(2)
-        for k in sorted(rng.choice(len(Q), 25, replace=False)):
-            s, v = oracle_answer(S, g, LS, Q.polygon(k))
+        say("[serve] oracle answers for every query")
+        want = oracle_answers(S, Q, g)
+        for k in range(len(Q)):
+            s, v = want[k]
             assert np.array_equal(mix[k].s_ids, s), k
             assert np.array_equal(mix[k].verdict, v), k
             assert mix[k].counts == np.bincount(v, minlength=3).tolist()
         total = sum(len(r.s_ids) for r in mix)
-        assert total > 1000
+        assert total > 100_000
+        allv = np.concatenate([w[1] for w in want])
+        assert set(np.unique(allv)) == {0, 1, 2}
         lat = np.array([r.latency for r in mix])
         assert np.all(lat > 0)
         say(f"[serve] {total} pairs; p50 {np.median(lat) * 1e3:.1f} ms")

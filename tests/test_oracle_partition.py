@@ -47,3 +47,19 @@ def test_finer_partitions_never_lose_decisions():
     r4, s4, v4 = oracle.partitioned_filter(synth.partitions.layout(R, S, 4, 10), R, S)
     assert np.array_equal(r1, r4) and np.array_equal(s1, s4)
     assert (v4 == oracle.IND).sum() <= (v1 == oracle.IND).sum()
+
+
+@pytest.mark.parametrize("k", [3, 16])
+def test_partitioned_pairs_are_instances_of_each_global_pair_once(k):
+    """partitioned_pairs names instances: mapped back to objects they are
+    the global MBR join, each pair once, and both instances of a pair sit in
+    the same partition."""
+    R, S, g = synth.configs.tiny()
+    lay = synth.partitions.layout(R, S, k, 10)
+    ri, si = oracle.partitioned_pairs(lay, R, S)
+    assert np.array_equal(lay.r_part()[ri], lay.s_part()[si])
+    ro, so = lay.r_obj[ri], lay.s_obj[si]
+    order = np.lexsort((so, ro))
+    want_r, want_s = oracle.mbr_join(R, S)
+    assert np.array_equal(ro[order], want_r.astype(np.int64))
+    assert np.array_equal(so[order], want_s.astype(np.int64))

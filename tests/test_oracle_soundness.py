@@ -109,3 +109,78 @@ def test_touching_polygons_are_not_negative():
     LB = oracle.build_lists(g, PolygonSet(b, np.array([0, 4], dtype=np.int64)))
     v = oracle.filter_pairs(LA, LB, [0], [0])
     assert v[0] != oracle.TN
+
+
+def _pip(poly, x, y):
+    return oracle.point_in_closed_polygon(poly, x * Q, y * Q)
+
+
+def test_point_in_closed_polygon_hand_cases():
+    """Closed point-in-polygon: the boundary counts as inside (R2's closed
+    sets).  Hand cases on a U shape (concave, with a notch) and a square."""
+    a = sq(0, 0, 10)
+    assert _pip(a, 5, 5)                 # inside
+    assert not _pip(a, 11, 5)            # outside, right
+    assert not _pip(a, -1, 5)            # outside, left
+    assert _pip(a, 10, 5)                # on an edge
+    assert _pip(a, 5, 0)                 # on the bottom edge
+    assert _pip(a, 0, 0) and _pip(a, 10, 10)    # on vertices
+    assert not _pip(a, 11, 0)            # on the bottom edge's extension
+    assert not _pip(a, 10, 11)           # on the right edge's extension
+    assert not _pip(a, 15, 10)           # level with the top edge, right of it
+    u = np.array([[0, 0], [30, 0], [30, 30], [20, 30], [20, 10], [10, 10], [10, 30], [0, 30]],
+                 dtype=np.float64) * Q
+    assert not _pip(u, 15, 20)           # in the notch
+    assert _pip(u, 15, 10)               # on the notch's floor
+    assert _pip(u, 20, 20)               # on the notch's wall
+    assert _pip(u, 5, 20) and _pip(u, 25, 20) and _pip(u, 15, 5)
+    assert not _pip(u, 15, 30)           # between the prongs at their tops
+    assert _pip(u, 10, 30) and _pip(u, 20, 30)   # prong corners
+    assert not _pip(u, 35, 30)           # level with the prong tops, right
+    assert not _pip(u, -5, 10)           # level with the notch floor, left
+    # a ray through a vertex: the point's ray towards +x passes a vertex
+    d = np.array([[10, 0], [20, 10], [10, 20], [0, 10]], dtype=np.float64) * Q
+    assert _pip(d, 5, 10) and _pip(d, 15, 10) and not _pip(d, -5, 10) and not _pip(d, 25, 10)
+    assert _pip(d, 0, 10) and _pip(d, 20, 10)    # the vertices on that line
+
+
+def _inside_union_of_rects(rects, x, y):
+    return any(x0 <= x <= x1 and y0 <= y <= y1 for x0, y0, x1, y1 in rects)
+
+
+def test_point_in_closed_polygon_closed_forms():
+    """Against closed forms on every lattice point of a window: a U shape is
+    the union of three closed rectangles; a convex polygon (counter-
+    clockwise) holds a point iff no edge has it strictly on its right."""
+    u = [[0, 0], [30, 0], [30, 30], [20, 30], [20, 10], [10, 10], [10, 30], [0, 30]]
+    rects = [(0, 0, 30, 10), (0, 0, 10, 30), (20, 0, 30, 30)]
+    up = np.array(u, dtype=np.float64) * Q
+    for x in range(-2, 33):
+        for y in range(-2, 33):
+            assert _pip(up, x, y) == _inside_union_of_rects(rects, x, y), (x, y)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        # a convex polygon: the hull of random lattice points, counter-clockwise
+        pts = rng.integers(0, 40, size=(12, 2))
+        pts = sorted(set(map(tuple, pts.tolist())))
+
+        def cross(o, a, b):
+            return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+        lower, upper = [], []
+        for p in pts:
+            while len(lower) >= 2 and cross(lower[-2], lower[-1], p) <= 0:
+                lower.pop()
+            lower.append(p)
+        for p in reversed(pts):
+            while len(upper) >= 2 and cross(upper[-2], upper[-1], p) <= 0:
+                upper.pop()
+            upper.append(p)
+        hull = lower[:-1] + upper[:-1]
+        if len(hull) < 3:
+            continue
+        hp = np.array(hull, dtype=np.float64) * Q
+        for x in range(-1, 42, 2):
+            for y in range(-1, 42, 2):
+                want = all(cross(hull[k], hull[(k + 1) % len(hull)], (x, y)) >= 0
+                           for k in range(len(hull)))
+                assert _pip(hp, x, y) == want, (hull, x, y)

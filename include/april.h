@@ -295,6 +295,29 @@ int april_filter_pairs(const april_lists_t *R, const april_lists_t *S, const uin
                        uint64_t *d_counts, const april_filter_opts_t *opts, void *hip_stream);
 
 /*
+ * april_filter_pairs for callers that cannot allocate device memory: code
+ * being captured into a HIP graph, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, verdicts and counts as
+ * april_filter_pairs, but it allocates nothing: its scratch (work counters
+ * and count slots) is a static device array of the library, 64 KiB per
+ * device plus a 256-byte flag word, held from the device's first library
+ * call until the process ends.  The device's address of that array is
+ * looked up once per device (hipGetSymbolAddress) at that first call.
+ *   opts        as for april_filter_pairs, except: d_workspace must be NULL
+ *               and workspace_bytes 0, APRIL_WS_DECODE_CACHE is refused
+ *   R, S        raw lists only (compressed lists need a decode cache)
+ * Every call on one device shares the array and leaves its contents behind;
+ * each call clears what it needs before its kernels read it (with a kernel,
+ * not a memset).  Two calls that overlap in time on one device (two streams,
+ * or two host threads) race on the array: serialize them.  Errors: those of
+ * april_filter_pairs, and APRIL_E_INVALID for a workspace, compressed lists,
+ * or a call whose scratch would exceed the static array.
+ */
+int april_filter_pairs_static(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                              const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
+                              uint64_t *d_counts, const april_filter_opts_t *opts, void *hip_stream);
+
+/*
  * Data movement of Alg. 2 itself, per pair: the bytes the sequential
  * AA -> AF -> FA merge-joins with early exit must read and write.
  * d_bytes[p] (device uint64[n_pairs]) = 8 (the pair's two uint32 ids)

@@ -115,6 +115,7 @@ def lib():
     L.april_lists_load.argtypes = [C.c_char_p, i32, C.POINTER(P)]
     L.april_lists_free.restype = None
     L.april_filter_pairs.argtypes = [P, P, P, P, u64, P, P, C.POINTER(april_filter_opts_t), P]
+    L.april_filter_pairs_static.argtypes = [P, P, P, P, u64, P, P, C.POINTER(april_filter_opts_t), P]
     L.april_alg2_bytes.argtypes = [P, P, P, P, u64, P, P]
     L.april_filter_workspace_size.argtypes = [u64, C.POINTER(april_filter_opts_t), C.POINTER(u64)]
     L.april_mbr_join.argtypes = [P, u64, P, u64, P, P, u64, C.POINTER(u64)]
@@ -146,7 +147,7 @@ def lib():
     L.april_last_error.restype = C.c_char_p
     for name in ("april_build_lists", "april_build_lists_partitioned", "april_build_lists_gpu", "april_lists_from_arrays", "april_lists_info",
                  "april_lists_export", "april_lists_to_device", "april_lists_download",
-                 "april_filter_pairs",
+                 "april_filter_pairs", "april_filter_pairs_static",
                  "april_alg2_bytes", "april_filter_workspace_size",
                  "april_mbr_join", "april_device_info", "april_serve_create",
                  "april_serve_submit", "april_serve_poll", "april_serve_wait", "april_serve_release",
@@ -323,6 +324,17 @@ def april_filter_pairs(R: Lists, S: Lists, r, s, verdict, counts=None, schedule=
     return _check(lib().april_filter_pairs(R.handle, S.handle, _dptr(r), _dptr(s), n,
                                            _dptr(verdict), _dptr(counts), C.byref(opts),
                                            _stream(stream)))
+
+
+def april_filter_pairs_static(R: Lists, S: Lists, r, s, verdict, counts=None, schedule=SCHED_PLAIN,
+                              flags=0, waves=0, stream=None, **tuning) -> int:
+    """april_filter_pairs on the library's static scratch: allocates nothing
+    (raw lists; no workspace)."""
+    n = int(r.numel()) if hasattr(r, "numel") else (0 if isinstance(r, int) else int(len(r)))
+    opts = _opts(schedule, flags, waves, **tuning)
+    return _check(lib().april_filter_pairs_static(R.handle, S.handle, _dptr(r), _dptr(s), n,
+                                                  _dptr(verdict), _dptr(counts), C.byref(opts),
+                                                  _stream(stream)))
 
 
 def april_alg2_bytes(R: Lists, S: Lists, r, s, bytes_out, stream=None) -> int:

@@ -52,6 +52,9 @@ constexpr uint32_t kCtrStride = 32;    // uint32 words per slot
 constexpr uint32_t kMaxCtrs = 64;
 constexpr uint32_t kSlotWords = 16;    // uint64 words per slot
 constexpr uint64_t kCtrBytes = 2ull * kMaxCtrs * kCtrStride * sizeof(unsigned int);
+// Workspace part of the static scratch (april_filter_pairs_static): enough
+// for any filter call's scratch on raw lists.
+constexpr uint64_t kStaticWorkspaceBytes = 64ull << 10;
 
 // zero both regions
 __global__ void k_zero_ctrs(unsigned int *ctr);

@@ -28,6 +28,18 @@
 #include "internal.hpp"
 
 namespace april {
+// Static scratch: the work counters and count slots of a filter call made
+// through april_filter_pairs_static (which allocates nothing), then the
+// one-word flag of index validation at kStaticFlagOffset (used by every
+// validating filter call).  One copy per device, held until the process
+// ends; all calls on a device share it.
+constexpr uint64_t kStaticFlagOffset = kStaticWorkspaceBytes;
+constexpr uint64_t kStaticScratchBytes = kStaticWorkspaceBytes + 256;
+}  // namespace april
+
+static __device__ __align__(256) unsigned char scratch[april::kStaticScratchBytes];
+
+namespace april {
 namespace {
 
 // Any overlap between X = [xs, xe)[0..n) and Y = [ys, ye)[0..m)?  Result is
@@ -184,6 +196,8 @@ __global__ void k_zero_counts(unsigned long long *c) {
     if (threadIdx.x < 3) c[threadIdx.x] = 0;
 }
 
+__global__ void k_clear_flag(unsigned int *f) { *f = 0; }
+
 __global__ void k_check_pairs(const uint32_t *r, const uint32_t *s, uint64_t n, uint64_t n_r,
                               uint64_t n_s, unsigned int *bad) {
     for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n;
@@ -206,7 +220,13 @@ int device_state(DeviceState **out) {
         APRIL_HIP_TRY(hipGetDeviceProperties(&p, dev));
         if (std::string(p.gcnArchName).rfind("gfx950", 0) != 0)
             return fail(APRIL_E_NODEV, std::string("library built for gfx950, device is ") + p.gcnArchName);
-        APRIL_HIP_TRY(hipMalloc(&st.flag, sizeof(unsigned int)));
+        // this device's copy of the static scratch (its own address on
+        // every device); host code uses only this address, never the
+        // array's name
+        void *ptr = nullptr;
+        APRIL_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        st.scratch = ptr;
+        st.flag = reinterpret_cast<unsigned int *>(static_cast<char *>(ptr) + kStaticFlagOffset);
         st.cus = p.multiProcessorCount;
     }
     *out = &st;
@@ -292,7 +312,8 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
         return APRIL_OK;
     }
     if (o.flags & APRIL_VALIDATE) {
-        APRIL_HIP_TRY(hipMemsetAsync(st->flag, 0, sizeof(unsigned int), stream));
+        k_clear_flag<<<1, 1, 0, stream>>>(st->flag);
+        APRIL_HIP_TRY(hipGetLastError());
         k_check_pairs<<<1024, 256, 0, stream>>>(d_r, d_s, n_pairs, R->n, S->n, st->flag);
         APRIL_HIP_TRY(hipGetLastError());
         unsigned int bad = 0;
@@ -373,6 +394,31 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
     }
     if (e != hipSuccess) return fail(APRIL_E_HIP, std::string("filter launch: ") + hipGetErrorString(e));
     return APRIL_OK;
+}
+
+extern "C" int april_filter_pairs_static(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                                         const uint32_t *d_s, uint64_t n_pairs, uint8_t *d_verdict,
+                                         uint64_t *d_counts, const april_filter_opts_t *opts,
+                                         void *hip_stream) {
+    clear_error();
+    april_filter_opts_t o{};
+    if (opts) o = *opts;
+    if (o.d_workspace || o.workspace_bytes)
+        return fail(APRIL_E_INVALID, "april_filter_pairs_static takes no workspace (it uses the static scratch)");
+    if (o.flags & APRIL_WS_DECODE_CACHE)
+        return fail(APRIL_E_INVALID, "april_filter_pairs_static has no decode cache");
+    if ((R && R->codec != APRIL_CODEC_RAW) || (S && S->codec != APRIL_CODEC_RAW))
+        return fail(APRIL_E_INVALID,
+                    "april_filter_pairs_static takes raw lists only (compressed lists need a decode cache)");
+    const uint64_t need = batched_workspace_bytes(n_pairs);
+    if (need > kStaticWorkspaceBytes)
+        return fail(APRIL_E_INVALID, "this call needs " + std::to_string(need) + " bytes of scratch; the static "
+                                     "scratch holds " + std::to_string(kStaticWorkspaceBytes));
+    DeviceState *st;
+    if (int rc = device_state(&st)) return rc;
+    o.d_workspace = st->scratch;
+    o.workspace_bytes = kStaticWorkspaceBytes;
+    return april_filter_pairs(R, S, d_r, d_s, n_pairs, d_verdict, d_counts, &o, hip_stream);
 }
 
 extern "C" int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opts,

@@ -129,10 +129,13 @@ int check_lists(uint64_t n, const uint64_t *off_a, const uint32_t *start_a, cons
 int build_lists_threads(const april_grid_t *grid, const double *xy, const uint64_t *vtx_off, uint64_t n,
                         uint32_t flags, int max_threads, april_lists_t **out);
 
-// Per-device state of the filter: compute-unit count and a one-word flag
-// used by index validation.  Created on first use on each device.
+// Per-device state of the filter, created on first use on each device (with
+// that device current): compute-unit count, the device address of this
+// device's static scratch (april_filter_pairs_static's workspace), and the
+// one-word flag of index validation inside it.
 struct DeviceState {
     int cus = 0;
+    void *scratch = nullptr;
     unsigned int *flag = nullptr;
 };
 int device_state(DeviceState **out);

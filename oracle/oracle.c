@@ -426,10 +426,18 @@ int orc_classify(double x0, double y0, double side, int order,
 /*
  * Classes of given cells of one polygon: cell t is (i, j) = (ij[2t],
  * ij[2t + 1]) and cls[t] gets CELL_EMPTY / CELL_PARTIAL / CELL_FULL, decided
- * by the same brute-force rule as orc_classify but over all of the
- * polygon's edges, for polygons whose whole cell window is too large to
- * classify (checks by sampled cells).
+ * by the same brute-force rule as orc_classify, for polygons whose whole
+ * cell window is too large to classify (checks by sampled cells).  As in
+ * orc_classify, the cells are taken row by row: an edge whose y-range misses
+ * the row cannot meet its cells, and only edges across the row's centre line
+ * can cross a centre's ray; every other edge is tested for every cell.
  */
+static int cmp_row(const void *a, const void *b)   /* (row, index) pairs by row */
+{
+    const int64_t ja = ((const int64_t *)a)[0], jb = ((const int64_t *)b)[0];
+    return ja < jb ? -1 : ja > jb;
+}
+
 int orc_classify_cells(double x0, double y0, double side, int order, const double *xy, int64_t nv,
                        const int64_t *ij, int64_t n, uint8_t *cls)
 {
@@ -442,29 +450,48 @@ int orc_classify_cells(double x0, double y0, double side, int order, const doubl
     const int64_t W = g.W, m = p.nv;
     int64_t *X2 = (int64_t *)malloc(sizeof(int64_t) * m);
     int64_t *Y2 = (int64_t *)malloc(sizeof(int64_t) * m);
-    if (!X2 || !Y2) { free(X2); free(Y2); free(p.x); free(p.y); return ORC_E_NOMEM; }
+    int64_t *row = (int64_t *)malloc(sizeof(int64_t) * m);
+    int64_t *mid = (int64_t *)malloc(sizeof(int64_t) * m);
+    int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * 2 * (n ? n : 1));   /* (row, cell index) */
+    if (!X2 || !Y2 || !row || !mid || !ord) {
+        free(X2); free(Y2); free(row); free(mid); free(ord); free(p.x); free(p.y);
+        return ORC_E_NOMEM;
+    }
     for (int64_t k = 0; k < m; k++) { X2[k] = 2 * p.x[k]; Y2[k] = 2 * p.y[k]; }
-    for (int64_t t = 0; t < n; t++) {
-        const int64_t i = ij[2 * t], j = ij[2 * t + 1];
-        const int64_t bx0 = i * W, bx1 = (i + 1) * W, by0 = j * W, by1 = (j + 1) * W;
-        int open_touch = 0, closed_touch = 0;
-        for (int64_t k = 0; k < m && !open_touch; k++) {
-            int64_t k2 = (k + 1 == m) ? 0 : k + 1;
-            int64_t xlo = p.x[k] < p.x[k2] ? p.x[k] : p.x[k2], xhi = p.x[k] > p.x[k2] ? p.x[k] : p.x[k2];
-            int64_t ylo = p.y[k] < p.y[k2] ? p.y[k] : p.y[k2], yhi = p.y[k] > p.y[k2] ? p.y[k] : p.y[k2];
-            if (xhi < bx0 || xlo > bx1 || yhi < by0 || ylo > by1) continue;
-            if (seg_meets_box(p.x[k], p.y[k], p.x[k2], p.y[k2], bx0, by0, bx1, by1, 1))
-                open_touch = 1;
-            else if (!closed_touch && seg_meets_box(p.x[k], p.y[k], p.x[k2], p.y[k2], bx0, by0, bx1, by1, 0))
-                closed_touch = 1;
+    /* cells grouped by row (the order within a row does not matter) */
+    for (int64_t t = 0; t < n; t++) { ord[2 * t] = ij[2 * t + 1]; ord[2 * t + 1] = t; }
+    qsort(ord, (size_t)n, 2 * sizeof(int64_t), cmp_row);
+    for (int64_t u = 0; u < n;) {
+        const int64_t j = ord[2 * u];
+        const int64_t by0 = j * W, by1 = (j + 1) * W, yc2 = (2 * j + 1) * W;
+        int64_t nrow = 0, nmid = 0;
+        for (int64_t k = 0; k < m; k++) {
+            const int64_t k2 = (k + 1 == m) ? 0 : k + 1;
+            const int64_t ylo = p.y[k] < p.y[k2] ? p.y[k] : p.y[k2], yhi = p.y[k] > p.y[k2] ? p.y[k] : p.y[k2];
+            if (yhi >= by0 && ylo <= by1) row[nrow++] = k;
+            if ((Y2[k] > yc2) != (Y2[k2] > yc2)) mid[nmid++] = k;
         }
-        if (open_touch) cls[t] = CELL_PARTIAL;
-        else {
-            int in = crossing_inside(X2, Y2, m, NULL, m, (2 * i + 1) * W, (2 * j + 1) * W);
-            cls[t] = in ? CELL_FULL : (closed_touch ? CELL_PARTIAL : CELL_EMPTY);
+        for (; u < n && ord[2 * u] == j; u++) {
+            const int64_t t = ord[2 * u + 1], i = ij[2 * t];
+            const int64_t bx0 = i * W, bx1 = (i + 1) * W;
+            int open_touch = 0, closed_touch = 0;
+            for (int64_t q = 0; q < nrow && !open_touch; q++) {
+                const int64_t k = row[q], k2 = (k + 1 == m) ? 0 : k + 1;
+                const int64_t xlo = p.x[k] < p.x[k2] ? p.x[k] : p.x[k2], xhi = p.x[k] > p.x[k2] ? p.x[k] : p.x[k2];
+                if (xhi < bx0 || xlo > bx1) continue;
+                if (seg_meets_box(p.x[k], p.y[k], p.x[k2], p.y[k2], bx0, by0, bx1, by1, 1))
+                    open_touch = 1;
+                else if (!closed_touch && seg_meets_box(p.x[k], p.y[k], p.x[k2], p.y[k2], bx0, by0, bx1, by1, 0))
+                    closed_touch = 1;
+            }
+            if (open_touch) cls[t] = CELL_PARTIAL;
+            else {
+                const int in = crossing_inside(X2, Y2, m, mid, nmid, (2 * i + 1) * W, yc2);
+                cls[t] = in ? CELL_FULL : (closed_touch ? CELL_PARTIAL : CELL_EMPTY);
+            }
         }
     }
-    free(X2); free(Y2); free(p.x); free(p.y);
+    free(X2); free(Y2); free(row); free(mid); free(ord); free(p.x); free(p.y);
     return ORC_OK;
 }
 

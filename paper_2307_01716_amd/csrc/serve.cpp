@@ -24,6 +24,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "internal.hpp"
@@ -38,6 +39,12 @@ double now_s() {
 
 enum ReqState { RQ_QUEUED, RQ_BUILT, RQ_RUNNING, RQ_DONE, RQ_FAILED };
 
+// A request is shared by whoever holds it: the ticket table, a queue, a
+// builder thread, a slot's batch, and callers blocked in april_serve_wait.
+// It is freed with the last of them, so a cancel or a release never frees a
+// request another thread still reads.  Every field is read and written under
+// the server's mutex, except the query and the lists, which only the thread
+// holding the request in its stage touches.
 struct Req {
     uint64_t ticket = 0;
     std::vector<double> xy;
@@ -46,20 +53,24 @@ struct Req {
     uint64_t pair_bound = 0;
     int state = RQ_QUEUED;
     int rc = APRIL_OK;
-    bool cancelled = false;
+    bool cancelled = false;           // cancelled: no longer in the ticket table
     double t_submit = 0, t_built = 0, t_done = 0;
     std::vector<uint32_t> s_ids;
     std::vector<uint8_t> verdict;
     uint64_t counts[3] = {0, 0, 0};
+    ~Req() {
+        if (lists) april_lists_free(lists);
+    }
 };
+using ReqPtr = std::shared_ptr<Req>;
 
 enum SlotState { SL_FREE, SL_PROBING, SL_FILTERING };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    int state = SL_FREE;
-    std::vector<Req *> batch;
+    int state = SL_FREE;      // written by the dispatcher under the server's mutex
+    std::vector<ReqPtr> batch;
     uint64_t n_pairs = 0;
     // device
     void *d_block = nullptr;
@@ -103,8 +114,8 @@ struct april_server {
     // requests
     std::mutex mu;
     std::condition_variable cv_build, cv_dispatch, cv_done;
-    std::deque<Req *> to_build, ready;
-    std::map<uint64_t, Req *> reqs;
+    std::deque<ReqPtr> to_build, ready;
+    std::map<uint64_t, ReqPtr> reqs;   // live tickets (not released, not cancelled)
     uint64_t next_ticket = 1;
     bool stop = false;
     std::vector<std::thread> builders;
@@ -149,7 +160,7 @@ void builder_main(april_server *sv) {
         }
     } guard{gpu_stream};
     for (;;) {
-        Req *q;
+        ReqPtr q;
         int threads = 1;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
@@ -202,12 +213,7 @@ void builder_main(april_server *sv) {
         sv->builders_busy--;
         q->lists = L;
         q->t_built = now_s();
-        if (q->cancelled) {   // cancelled while being built
-            if (L) april_lists_free(L);
-            sv->reqs.erase(q->ticket);
-            delete q;
-            continue;
-        }
+        if (q->cancelled) continue;   // cancelled while being built: dropped here
         if (rc != APRIL_OK) {
             q->rc = rc;
             q->state = RQ_FAILED;
@@ -260,6 +266,7 @@ int slot_phase_a(april_server *sv, Slot &sl) {
         return rc;
     APRIL_HIP_TRY(hipMemcpyAsync(sl.h_n, sl.d_n, sizeof(unsigned int), hipMemcpyDeviceToHost, sl.stream));
     APRIL_HIP_TRY(hipEventRecord(sl.ev, sl.stream));
+    std::lock_guard<std::mutex> lk(sv->mu);
     sl.state = SL_PROBING;
     return APRIL_OK;
 }
@@ -280,6 +287,7 @@ int slot_phase_b(april_server *sv, Slot &sl) {
         APRIL_HIP_TRY(hipMemcpyAsync(sl.h_v, sl.d_v, sl.n_pairs, hipMemcpyDeviceToHost, sl.stream));
     }
     APRIL_HIP_TRY(hipEventRecord(sl.ev, sl.stream));
+    std::lock_guard<std::mutex> lk(sv->mu);
     sl.state = SL_FILTERING;
     return APRIL_OK;
 }
@@ -298,7 +306,7 @@ void slot_finish(april_server *sv, Slot &sl) {
     const double t = now_s();
     std::lock_guard<std::mutex> lk(sv->mu);
     for (uint64_t k = 0; k < nq; k++) {
-        Req *q = sl.batch[k];
+        Req *q = sl.batch[k].get();
         std::vector<std::pair<uint32_t, uint8_t>> sv_pairs;
         sv_pairs.reserve(cnt[k + 1] - cnt[k]);
         for (uint64_t u = cnt[k]; u < cnt[k + 1]; u++) sv_pairs.emplace_back(sl.h_ps[idx[u]], sl.h_v[idx[u]]);
@@ -315,27 +323,19 @@ void slot_finish(april_server *sv, Slot &sl) {
         q->lists = nullptr;
         q->state = RQ_DONE;
         q->t_done = t;
-        if (q->cancelled) {
-            sv->reqs.erase(q->ticket);
-            delete q;
-        }
     }
-    sl.batch.clear();
+    sl.batch.clear();   // cancelled requests are freed here, unless a waiter still holds one
     sl.state = SL_FREE;
     sv->cv_done.notify_all();
 }
 
 void fail_batch(april_server *sv, Slot &sl, int rc) {
     std::lock_guard<std::mutex> lk(sv->mu);
-    for (Req *q : sl.batch) {
+    for (const ReqPtr &q : sl.batch) {
         q->rc = rc;
         q->state = RQ_FAILED;
         q->t_done = now_s();
         if (q->lists) { april_lists_free(q->lists); q->lists = nullptr; }
-        if (q->cancelled) {
-            sv->reqs.erase(q->ticket);
-            delete q;
-        }
     }
     sl.batch.clear();
     sl.state = SL_FREE;
@@ -367,7 +367,7 @@ void dispatcher_main(april_server *sv) {
             std::unique_lock<std::mutex> lk(sv->mu);
             uint64_t pairs = 0, ivs = 0;
             while (!sv->ready.empty() && free_slot->batch.size() < sv->cap_queries) {
-                Req *q = sv->ready.front();
+                ReqPtr q = sv->ready.front();
                 if (q->cancelled) { sv->ready.pop_front(); continue; }
                 const uint64_t qi = q->lists->n_a + q->lists->n_f;
                 if (!free_slot->batch.empty() &&
@@ -470,11 +470,7 @@ void destroy(april_server *sv) {
         if (sl.h_block) (void)hipHostFree(sl.h_block);
     }
     if (sv->d_index) (void)hipFree(sv->d_index);
-    for (auto &kv : sv->reqs) {
-        if (kv.second->lists) april_lists_free(kv.second->lists);
-        delete kv.second;
-    }
-    delete sv;
+    delete sv;   // frees the requests no caller holds any more
 }
 
 }  // namespace
@@ -608,9 +604,13 @@ int april_serve_submit(april_server_t *sv, const double *xy, uint64_t n_vertices
     clear_error();
     if (!sv || !xy || !ticket) return fail(APRIL_E_INVALID, "NULL argument");
     if (n_vertices < 3) return fail(APRIL_E_INVALID, "query with < 3 vertices");
-    Req *q = new (std::nothrow) Req;
-    if (!q) return fail(APRIL_E_NOMEM, "out of host memory");
-    q->xy.assign(xy, xy + 2 * n_vertices);
+    ReqPtr q;
+    try {
+        q = std::make_shared<Req>();
+        q->xy.assign(xy, xy + 2 * n_vertices);
+    } catch (const std::bad_alloc &) {
+        return fail(APRIL_E_NOMEM, "out of host memory");
+    }
     q->t_submit = now_s();
     std::lock_guard<std::mutex> lk(sv->mu);
     q->ticket = sv->next_ticket++;
@@ -640,8 +640,8 @@ int april_serve_poll(april_server_t *sv, uint64_t ticket, april_result_t *out) {
     if (!sv || !out) return fail(APRIL_E_INVALID, "NULL argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end() || it->second->cancelled) return fail(APRIL_E_INVALID, "unknown ticket");
-    fill_result(it->second, out);
+    if (it == sv->reqs.end()) return fail(APRIL_E_INVALID, "unknown ticket");
+    fill_result(it->second.get(), out);
     if (out->status < 0) fail(out->status, "request failed");
     return out->status;
 }
@@ -651,11 +651,12 @@ int april_serve_wait(april_server_t *sv, uint64_t ticket, double timeout_s, apri
     if (!sv || !out) return fail(APRIL_E_INVALID, "NULL argument");
     std::unique_lock<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end() || it->second->cancelled) return fail(APRIL_E_INVALID, "unknown ticket");
-    Req *q = it->second;
+    if (it == sv->reqs.end()) return fail(APRIL_E_INVALID, "unknown ticket");
+    const ReqPtr q = it->second;   // held while waiting: a cancel or release cannot free it
     sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                         [&] { return q->state == RQ_DONE || q->state == RQ_FAILED; });
-    fill_result(q, out);
+                         [&] { return q->cancelled || q->state == RQ_DONE || q->state == RQ_FAILED; });
+    if (q->cancelled || !sv->reqs.count(ticket)) return fail(APRIL_E_INVALID, "request cancelled or released");
+    fill_result(q.get(), out);
     if (out->status < 0) fail(out->status, "request failed");
     return out->status;
 }
@@ -666,11 +667,9 @@ int april_serve_release(april_server_t *sv, uint64_t ticket) {
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
     if (it == sv->reqs.end()) return fail(APRIL_E_INVALID, "unknown ticket");
-    Req *q = it->second;
+    const Req *q = it->second.get();
     if (q->state != RQ_DONE && q->state != RQ_FAILED) return fail(APRIL_E_INVALID, "request still pending");
-    if (q->lists) april_lists_free(q->lists);
-    sv->reqs.erase(it);
-    delete q;
+    sv->reqs.erase(it);   // freed with the last holder
     return APRIL_OK;
 }
 
@@ -679,25 +678,17 @@ int april_serve_cancel(april_server_t *sv, uint64_t ticket) {
     if (!sv) return fail(APRIL_E_INVALID, "NULL argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->reqs.find(ticket);
-    if (it == sv->reqs.end() || it->second->cancelled) return fail(APRIL_E_INVALID, "unknown ticket");
-    Req *q = it->second;
-    bool held = q->state == RQ_RUNNING;   // on the GPU: dropped when its batch ends
-    if (q->state == RQ_QUEUED || q->state == RQ_BUILT) {
-        // still in a queue, or held by a builder (then the builder drops it)
-        bool queued = false;
-        for (auto *dq : {&sv->to_build, &sv->ready}) {
-            auto f = std::find(dq->begin(), dq->end(), q);
-            if (f != dq->end()) { dq->erase(f); queued = true; }
-        }
-        held = !queued;
+    if (it == sv->reqs.end()) return fail(APRIL_E_INVALID, "unknown ticket");
+    const ReqPtr q = it->second;
+    // out of the ticket table and the queues; a builder or a slot holding it
+    // drops it when its stage ends, a waiter wakes and reports the cancel
+    q->cancelled = true;
+    for (auto *dq : {&sv->to_build, &sv->ready}) {
+        auto f = std::find(dq->begin(), dq->end(), q);
+        if (f != dq->end()) dq->erase(f);
     }
-    if (held) {
-        q->cancelled = true;
-        return APRIL_OK;
-    }
-    if (q->lists) april_lists_free(q->lists);
     sv->reqs.erase(it);
-    delete q;
+    sv->cv_done.notify_all();
     return APRIL_OK;
 }
 

@@ -77,6 +77,14 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="offered arrivals per load level last about this long (at most 10^4 queries)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--tune-table", default=os.path.join(HERE, "paper_2307_01716_amd", "tuning", "mi355x.json"),
+                    help="stored batched settings (device x workload signature) used instead of a sweep")
+    ap.add_argument("--retune", action="store_true", help="sweep even when the table has the workload")
+    ap.add_argument("--tune-out", default="", help="store swept settings in this table")
+    ap.add_argument("--no-skewed", action="store_true",
+                    help="skip the skewed workload's leg of the default run")
+    ap.add_argument("--skewed-no-plain", action="store_true",
+                    help="skewed leg: batched form only")
     return ap.parse_args()
 
 
@@ -116,11 +124,197 @@ def cpu_baseline(R, S, g, seconds):
         t1s.append(time.perf_counter() - t1)
     single = len(r) / float(np.median(t1s))
     return {"value": value, "unit": "pairs/s", "cores": int(used), "kind": "oracle",
-            "single_thread_value": single,
+            "single_thread_value": single, "cpu": cpu_model(),
             "sample": (f"all {len(r)} candidate pairs among the {len(inR)} R and {len(inS)} S "
                        f"objects whose MBR centres lie in a {2 * half:.4f}-wide square window; "
                        f"filter repeated {reps}x ({t_filter:.1f} s); list build {build_s:.1f} s "
                        "not timed")}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def gpu_lists(april, g, P, max_vertices=16_000_000):
+    """Lists of polygon set P built on the GPU in chunks of consecutive
+    polygons (each chunk's build scratch then fits the device), read back and
+    joined into one host collection."""
+    parts = []
+    v = P.voff
+    k = 0
+    n = len(v) - 1
+    while k < n:
+        e = int(np.searchsorted(v, v[k] + max_vertices, side="right")) - 1
+        e = max(e, k + 1)
+        e = min(e, n)
+        sub = P.subset(np.arange(k, e))
+        d = april.april_build_lists_gpu(g, sub.xy, sub.voff, april.STRICT)
+        parts.append(april.april_lists_download(d).export())
+        d.free()
+        k = e
+    offA, sA, eA, offF, sF, eF = [], [], [], [], [], []
+    ba = bf = 0
+    for i, (oa, sa, ea, of, sf, ef) in enumerate(parts):
+        offA.append(oa[(1 if i else 0):] + np.uint64(ba))
+        offF.append(of[(1 if i else 0):] + np.uint64(bf))
+        sA.append(sa), eA.append(ea), sF.append(sf), eF.append(ef)
+        ba += len(sa)
+        bf += len(sf)
+    cat = np.concatenate
+    return april.april_lists_from_arrays(g, cat(offA), cat(sA), cat(eA), cat(offF), cat(sF), cat(eF),
+                                         validate=False)
+
+
+def calibration_copies():
+    """Three 1 GiB device-to-device copies: reference dispatches of known
+    size for the HBM byte counters (FETCH_SIZE, WRITE_SIZE)."""
+    import torch
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x 1 GiB device-to-device copies")
+
+
+def autotune(tune, dR, dS, r, s, verdict, counts, ws, sig, args):
+    """Sweep the batched schedule's knobs; keep the library defaults unless
+    the best setting is more than 1% faster; store the result under
+    --tune-out (keyed by device and workload signature)."""
+    t0 = time.time()
+    cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3, log=log)
+    dflt_ms = tune.time_config(dR, dS, r, s, verdict, counts, ws, reps=3)
+    log(f"autotune: {len(table)} settings in {time.time() - t0:.1f}s; best {cfg} "
+        f"({best_ms:.3f} ms); library defaults {dflt_ms:.3f} ms")
+    if best_ms > 0.99 * dflt_ms:   # not clearly better: keep the defaults
+        cfg, best_ms = {}, dflt_ms
+    if args.tune_out:
+        tune.save(args.tune_out, tune.device_key(), sig, cfg, best_ms, table)
+    return cfg, "sweep"
+
+
+def skewed_leg(args, stream):
+    """The skewed workload: batched (hipGraph replay) and plain forms on all
+    ~30M pairs, the workgroup bin's share and the schedule's tail, measured
+    HBM traffic when a record for the current kernel exists."""
+    import torch
+
+    import synth
+    from paper_2307_01716_amd import april, profiling, tune
+
+    t0 = time.time()
+    R, S, g = synth.configs.skewed()
+    log(f"skewed: generated R={len(R)} S={len(S)} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    hR, hS = gpu_lists(april, g, R), gpu_lists(april, g, S)
+    log(f"skewed: lists built on the GPU (A={hR.info().n_a + hS.info().n_a}) in {time.time() - t0:.1f}s")
+    r_np, s_np = april.april_mbr_join(R.mbrs(), S.mbrs())
+    P = len(r_np)
+    # the bins, from the list lengths (as the library's binning pass decides)
+    oR, oS = hR.export(), hS.export()
+    mr = np.maximum(np.diff(oR[0].astype(np.int64)), np.diff(oR[3].astype(np.int64)))[r_np]
+    ms = np.maximum(np.diff(oS[0].astype(np.int64)), np.diff(oS[3].astype(np.int64)))[s_np]
+    del oR, oS, R, S
+    dR = april.april_lists_to_device(hR, stream=stream)
+    dS = april.april_lists_to_device(hS, stream=stream)
+    r = torch.from_numpy(r_np.view(np.int32)).cuda()
+    s = torch.from_numpy(s_np.view(np.int32)).cuda()
+    verdict = torch.empty(P, dtype=torch.uint8, device="cuda")
+    counts = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    sig = tune.signature(P, dR, dS)
+    cfg = tune.load(args.tune_table, tune.device_key(), sig)
+    src = "tuning table"
+    if cfg is None or args.retune:
+        cfg, src = {}, "library defaults"
+        if not args.no_tune:
+            cfg, src = autotune(tune, dR, dS, r, s, verdict, counts, ws, sig, args)
+    kw = tune.call_config(cfg)
+    tile = cfg.get("tile") or (256 if (hR.info().n_a + hS.info().n_a) <= 256 * (len(hR) + len(hS)) else 512)
+    wg_min = cfg.get("wg_min") or 4096
+    in_wg = (mr >= tile) & (ms >= tile) & (np.minimum(mr, ms) >= wg_min)
+    log(f"skewed: {P} pairs; setting {cfg} ({src}); workgroup bin {int(in_wg.sum())} pairs")
+
+    def run(flags=0):
+        april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_BATCHED,
+                                 workspace=ws, stream=stream, flags=flags, **kw)
+
+    run()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(stream)
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_BATCHED,
+                                     workspace=ws, stream=torch.cuda.current_stream(), **kw)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    ts = []
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        graph.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms_b = float(np.mean(ts))
+    c = counts.cpu().numpy()
+    assert int(c.sum()) == P
+    batched_v = verdict.clone()
+    # the schedule's tail: wavefront end times of one eager launch
+    run(april.WAVE_TIMES)
+    torch.cuda.synchronize()
+    t = ws[april.WAVE_TIMES_OFFSET:april.WAVE_TIMES_OFFSET + 24].cpu().numpy().view(np.uint64)
+    span = float(t[2] - t[0])
+    tail_frac = float(t[2] - t[1]) / span if span > 0 else 0.0
+    out = {"workload": "skewed: 200k x 200k star polygons plus 2000 x 2000 with 20k-100k vertices "
+                       "(radius 0.02-0.1), grid 2^16, all MBR candidate pairs",
+           "pairs": P, "verdicts": {"TN": int(c[0]), "TH": int(c[1]), "IND": int(c[2])},
+           "batched": {"kernel_ms": ms_b, "kernel_ms_median": float(np.median(ts)),
+                       "kernel_ms_p10": float(np.percentile(ts, 10)),
+                       "kernel_ms_p90": float(np.percentile(ts, 90)), "steps": steps,
+                       "pairs_per_s": P / (ms_b / 1e3), "hipgraph": True, "tuning": cfg,
+                       "tuning_source": src, "workgroup_bin_pairs": int(in_wg.sum()),
+                       "tail_ms": tail_frac * ms_b, "tail_frac": tail_frac}}
+    log(f"skewed batched: {ms_b:.2f} ms ({P / ms_b / 1e6:.0f} M pairs/s); tail {tail_frac * ms_b:.2f} ms "
+        f"({tail_frac:.1%}); TN/TH/IND = {c.tolist()}")
+    kname = "k_batched"
+    tr = profiling.read_traffic(os.path.join(HERE, "profiles", f"{kname}_skewed_traffic.txt"), kname, cfg, P)
+    if tr is not None:
+        out["batched"]["traffic_bytes"] = tr
+        out["batched"]["hbm_GBps"] = tr / (ms_b / 1e3) / 1e9
+        out["batched"]["hbm_frac"] = out["batched"]["hbm_GBps"] / HBM_PEAK_GBS
+    else:
+        out["batched"]["traffic_bytes"] = None
+    if not args.skewed_no_plain:
+        ts = []
+        for k in range(2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_PLAIN, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        assert torch.equal(verdict, batched_v), "skewed: batched and plain verdicts differ"
+        out["plain"] = {"kernel_ms": float(np.mean(ts)), "pairs_per_s": P / (np.mean(ts) / 1e3), "steps": 2}
+        out["batched"]["speedup_vs_plain"] = out["plain"]["kernel_ms"] / ms_b
+        log(f"skewed plain: {out['plain']['kernel_ms']:.1f} ms; batched speedup "
+            f"{out['batched']['speedup_vs_plain']:.1f}x")
+    del dR, dS, ws, r, s, verdict
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve_bench(args):
@@ -595,13 +789,7 @@ def main():
         return
     if args.partitioned:
         if args.copy_calibration:
-            import torch
-            src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-            dst = torch.empty_like(src)
-            for _ in range(3):
-                dst.copy_(src)
-            torch.cuda.synchronize()
-            del src, dst
+            calibration_copies()
         partitioned_bench(args)
         return
     import torch
@@ -612,9 +800,21 @@ def main():
     assert torch.cuda.is_available(), "no HIP device"
     dev = april.april_device_info()
     log(f"device: {dev['name']} {dev['arch']} CUs={dev['compute_units']}")
+    if args.workload == "skewed":
+        if args.copy_calibration:
+            calibration_copies()
+        sk = skewed_leg(args, torch.cuda.current_stream())
+        b = sk["batched"]
+        print(json.dumps({"metric": "candidate pairs filtered/s (skewed workload, batched, hipGraph replay)",
+                          "value": b["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": b["steps"],
+                          "warmup": args.warmup, "ms_per_step": b["kernel_ms"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+                          "config": {"workload": sk["workload"], "pairs": sk["pairs"]}, "forms": {"skewed": sk}}),
+              flush=True)
+        return
 
     t0 = time.time()
-    R, S, g = synth.configs.scale() if args.workload == "scale" else synth.configs.skewed()
+    R, S, g = synth.configs.scale()
     log(f"generated R={len(R)} S={len(S)} in {time.time() - t0:.1f}s")
     t0 = time.time()
     hR = april.april_build_lists(g, R.xy, R.voff, april.STRICT)
@@ -675,13 +875,7 @@ def main():
         return d
 
     if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy calibration: 3 x 1 GiB device-to-device copies")
+        calibration_copies()
 
     forms = {}
     if args.schedule in ("both", "plain"):
@@ -694,19 +888,18 @@ def main():
     if args.schedule in ("both", "batched"):
         from paper_2307_01716_amd import tune
         ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
-        cfg, kw = {}, {}
+        cfg, kw, tune_src = {}, {}, "library defaults"
+        sig = tune.signature(P, dR, dS)
+        stored = tune.load(args.tune_table, tune.device_key(), sig)
         if args.config:
             cfg = {k: int(v) for k, v in (kv.split("=") for kv in args.config.split(","))}
-            kw = tune.call_config(cfg)
+            tune_src = "--config"
+        elif stored is not None and not args.retune:
+            cfg, tune_src = stored, "tuning table"
         elif not args.no_tune:
-            t0 = time.time()
-            cfg, best_ms, table = tune.sweep(dR, dS, r, s, verdict, counts, ws, reps=3, log=log)
-            dflt_ms = tune.time_config(dR, dS, r, s, verdict, counts, ws, reps=3)
-            log(f"autotune: {len(table)} settings in {time.time() - t0:.1f}s; best {cfg} "
-                f"({best_ms:.3f} ms); library defaults {dflt_ms:.3f} ms")
-            if best_ms > 0.99 * dflt_ms:   # not clearly better: keep the defaults
-                cfg = {}
-            kw = tune.call_config(cfg)
+            cfg, tune_src = autotune(tune, dR, dS, r, s, verdict, counts, ws, sig, args)
+        kw = tune.call_config(cfg)
+        log(f"batched setting {cfg} ({tune_src})")
 
         def batched_eager():
             april.april_filter_pairs(dR, dS, r, s, verdict, counts, schedule=april.SCHED_BATCHED,
@@ -729,6 +922,7 @@ def main():
             fn = graph.replay
         forms["batched"] = form("batched", *timed(fn, args.steps, args.warmup))
         forms["batched"]["tuning"] = cfg
+        forms["batched"]["tuning_source"] = tune_src
         forms["batched"]["hipgraph"] = not args.no_graph
         if not args.no_random_order:
             # the same pairs in a seeded random order (no spatial locality
@@ -796,6 +990,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(R, S, g, args.cpu_seconds)
         log(f"cpu baseline: {out['cpu_baseline']['value'] / 1e6:.2f} M pairs/s "
             f"on {out['cpu_baseline']['cores']} threads ({time.time() - t0:.1f}s)")
+    if not args.no_skewed and args.workload == "scale":
+        del dR, dS
+        torch.cuda.synchronize()
+        out["forms"]["skewed"] = skewed_leg(args, stream)
     print(json.dumps(out), flush=True)
 
 

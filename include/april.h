@@ -216,13 +216,21 @@ int april_lists_load(const char *path, int validate, april_lists_t **out);
 #define APRIL_SCHED_BATCHED 1u  /* length-binned persistent schedule */
 
 #define APRIL_VALIDATE 1u       /* check indices first; synchronous; APRIL_E_INVALID */
+#define APRIL_WAVE_TIMES 4u      /* batched schedule on raw lists, caller workspace: five uint64 at
+                                    byte APRIL_WAVE_TIMES_OFFSET of the workspace receive, in
+                                    ticks of the device's real-time clock, the call's start, the
+                                    earliest and latest wavefront end of its wave kernel, and the
+                                    earliest and latest wavefront end of its workgroup-bin kernel
+                                    (~0 and 0 when it does not run); a
+                                    kernel's latest end - earliest end is its tail */
+#define APRIL_WAVE_TIMES_OFFSET 24448u
 #define APRIL_WS_DECODE_CACHE 2u /* compressed lists: the workspace also holds the decode
                                     cache (april_filter_workspace_size counts it when this
                                     flag is set), so the call allocates nothing */
 
 typedef struct {
     uint32_t schedule;     /* APRIL_SCHED_* */
-    uint32_t flags;        /* APRIL_VALIDATE | APRIL_WS_DECODE_CACHE */
+    uint32_t flags;        /* APRIL_VALIDATE | APRIL_WS_DECODE_CACHE | APRIL_WAVE_TIMES */
     uint32_t waves;        /* resident wavefronts (0 = library default) */
     uint32_t tile;         /* batched: intervals per list kept in LDS per wavefront:
                               128, 256 or 512 (0 = 256 when the two collections' A-lists
@@ -236,7 +244,14 @@ typedef struct {
     uint32_t search_min;   /* batched: streamed lists longer than this are first narrowed
                               to the resident list's Hilbert range by a 64-ary search
                               (0 = 512; compressed lists: 64) */
-    uint32_t reserved;     /* must be 0 */
+    uint32_t wg_min;       /* batched, raw lists: the workgroup bin.  Pairs in which both
+                              objects have a list of at least `tile` intervals and the
+                              shorter object's longer list holds at least wg_min run on a
+                              whole workgroup, whose four wavefronts share one tile four
+                              times as long and split the other object's stream; a binning
+                              pass queues them first (0 = 4096; 0xFFFFFFFF = never; no
+                              binning pass either when a collection uploaded from host lists
+                              has no object that long) */
     void *d_workspace;     /* device scratch of april_filter_workspace_size() bytes
                               (work counters; count sums), or NULL to let the library
                               allocate it (stream-ordered) when it needs it; pass one to
@@ -259,7 +274,11 @@ int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opt
  * Schedules (the verdicts are identical):
  *   APRIL_SCHED_PLAIN    one wavefront per pair; the three joins run as
  *                        merge paths over LDS tiles of both lists.
- *   APRIL_SCHED_BATCHED  one persistent kernel takes the pairs in input
+ *   APRIL_SCHED_BATCHED  pairs are binned by list length.  A binning
+ *                        pass queues the pairs of two long objects (see
+ *                        wg_min), and a persistent kernel joins each on the
+ *                        four wavefronts of a workgroup.  Then one
+ *                        persistent kernel takes the other pairs in input
  *                        order (each XCD its own range first): one
  *                        wavefront per pair keeps one object's lists in LDS
  *                        (reused while consecutive pairs share the object;
@@ -298,11 +317,12 @@ int april_filter_pairs(const april_lists_t *R, const april_lists_t *S, const uin
  * april_filter_pairs for callers that cannot allocate device memory: code
  * being captured into a HIP graph, tight serving loops, harnesses that
  * forbid allocation.  Same arguments, verdicts and counts as
- * april_filter_pairs, but it allocates nothing: its scratch (work counters
- * and count slots) is a static device array of the library, 64 KiB per
- * device plus a 256-byte flag word, held from the device's first library
- * call until the process ends.  The device's address of that array is
- * looked up once per device (hipGetSymbolAddress) at that first call.
+ * april_filter_pairs, but it allocates nothing: its scratch (work counters,
+ * count slots, the batched schedule's workgroup queues) is a static device
+ * array of the library, 4 MiB + 64 KiB per device plus a 256-byte flag word,
+ * held from the device's first library call until the process ends.  The
+ * device's address of that array is looked up once per device
+ * (hipGetSymbolAddress) at that first call.
  *   opts        as for april_filter_pairs, except: d_workspace must be NULL
  *               and workspace_bytes 0, APRIL_WS_DECODE_CACHE is refused
  *   R, S        raw lists only (compressed lists need a decode cache)

@@ -26,6 +26,8 @@ CODEC_RAW, CODEC_VBYTE = 0, 1
 SCHED_PLAIN, SCHED_BATCHED = 0, 1
 VALIDATE = 1
 WS_DECODE_CACHE = 2
+WAVE_TIMES = 4
+WAVE_TIMES_OFFSET = 24448
 
 _ERRNAMES = {E_INVALID: "APRIL_E_INVALID", E_GRID: "APRIL_E_GRID", E_NOMEM: "APRIL_E_NOMEM",
              E_HIP: "APRIL_E_HIP", E_CORRUPT: "APRIL_E_CORRUPT", E_NODEV: "APRIL_E_NODEV",
@@ -51,7 +53,7 @@ class april_lists_info_t(C.Structure):
 class april_filter_opts_t(C.Structure):
     _fields_ = [("schedule", C.c_uint32), ("flags", C.c_uint32), ("waves", C.c_uint32),
                 ("tile", C.c_uint32), ("chunk", C.c_uint32), ("thread_max", C.c_uint32),
-                ("search_min", C.c_uint32), ("reserved", C.c_uint32),
+                ("search_min", C.c_uint32), ("wg_min", C.c_uint32),
                 ("d_workspace", C.c_void_p), ("workspace_bytes", C.c_uint64)]
 
 
@@ -280,11 +282,11 @@ def april_lists_to_device(host: Lists, codec: int = CODEC_RAW, stream=None) -> L
 
 
 def _opts(schedule=SCHED_PLAIN, flags=0, waves=0, tile=0, chunk=0, thread_max=0, search_min=0,
-          workspace=None):
+          wg_min=0, workspace=None):
     ws = _dptr(workspace) if workspace is not None else None
     nbytes = int(workspace.numel() * workspace.element_size()) if hasattr(workspace, "numel") else 0
     return april_filter_opts_t(schedule, flags, waves, tile, chunk, thread_max, search_min,
-                               0, ws, nbytes)
+                               wg_min, ws, nbytes)
 
 
 def april_filter_workspace_size(n_pairs: int, schedule=SCHED_BATCHED, flags=0) -> int:

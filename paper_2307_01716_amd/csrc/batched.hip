@@ -1,4 +1,5 @@
-// Batched schedule of the APRIL filter: length binning + one persistent kernel.
+// Batched schedule of the APRIL filter: a length-binning pass, a persistent
+// kernel for the workgroup bin, and a persistent kernel for everything else.
 //
 // Join kernel used here.  For sorted, disjoint interval lists X and Y,
 // IntervalJoin of Alg. 2 returns true iff some X_i overlaps some Y_j.  That
@@ -38,11 +39,13 @@
 // p, because both elements meet that range; the F-inside-A argument above
 // holds per piece for the same reason.
 //
-// Work distribution: one persistent kernel, every pair handled by one wave,
-// in input order (pairs close in the input share lists, and the library's
-// MBR join emits them grouped by R object).  Each XCD drains its own
-// contiguous range of the input (so those lists meet in that XCD's L2),
-// then helps the others.  A wave takes `grab` pairs at a time, one lane per
+// Work distribution.  Pairs of two long objects (the workgroup bin, see
+// "binning" below) are queued by a binning pass and joined first, each by
+// the four waves of a workgroup.  Every other pair is handled by one wave of
+// a second persistent kernel, in input order (pairs close in the input share
+// lists, and the library's MBR join emits them grouped by R object).  Each
+// XCD drains its own contiguous range of the input (so those lists meet in
+// that XCD's L2), then helps the others.  A wave takes `grab` pairs at a time, one lane per
 // pair's metadata, and fewer once the range is nearly drained so that waves
 // finish together.  The object whose lists fit a tile is resident (R when
 // both do, kept while consecutive pairs share it); when neither fits, the
@@ -76,9 +79,90 @@ struct BatchArgs {
     uint32_t tail_grab;          // pairs per grab near a range's end
     uint64_t tail_pairs;         // "near the end": fewer pairs than this left
     uint32_t shift_r, shift_s;   // mixed orders: bits dropped from the finer side's A
+    // workgroup bin (Alg. 2 only): pairs whose shorter object spans at least
+    // wg_min intervals in a list (kNone: no workgroup bin)
+    uint32_t wg_min;
+    uint32_t qcap;               // queue entries per XCD range
+    unsigned int *qfill;         // big pairs binned into XCD k's queue: qfill[k * kCtrStride]
+    unsigned int *qhead;         // queue entries taken by workgroups: qhead[k * kCtrStride]
+    uint32_t *queue;             // XCD k's queue: queue[k * qcap ...]
+    unsigned long long *times;   // APRIL_WAVE_TIMES: call start; first, last end of the wave
+                                 // kernel; first, last end of the workgroup kernel (or null)
 };
 
 // ---------------------------------------------------------------- binning
+//
+// Every pair falls in one bin, decided from its four list lengths alone (so
+// the binning pass and the persistent kernel agree without a per-pair
+// table).  With mr, ms the longer of each object's A and F lengths:
+//   lane       both objects' lists have at most thread_max intervals:
+//              one lane runs Alg. 2 sequentially;
+//   workgroup  neither object fits a wave's tile and the shorter one spans
+//              at least wg_min intervals (Alg. 2 mode only): the four waves
+//              of a workgroup share one resident tile four times a wave's,
+//              cut into pieces by Hilbert key, and split the other object's
+//              stream between them;
+//   wave       everything else: one wave, the object that fits resident (or
+//              pieces of the shorter one).
+// The binning pass appends the workgroup bin's pairs to one queue per XCD
+// range (the range holding the pair) and marks their verdict bytes; a pair
+// that finds its queue full is marked for the wave bin instead.
+constexpr uint8_t kQueued = 0xFE;     // verdict byte of a pair in a workgroup queue
+constexpr uint8_t kOverflow = 0xFD;   // verdict byte of a workgroup-bin pair left to the wave bin
+
+__device__ __forceinline__ bool wg_bin(uint32_t mr, uint32_t ms, uint32_t tile, uint32_t wg_min) {
+    return mr >= tile && ms >= tile && min(mr, ms) >= wg_min;
+}
+
+// XCD range of pair p: the k with n * k / xcds <= p < n * (k + 1) / xcds
+__device__ __forceinline__ uint32_t range_of(uint64_t p, uint64_t n, uint32_t xcds) {
+    uint32_t k = uint32_t((p * xcds) / n);
+    if (k > 0 && p < n * k / xcds) k--;
+    if (k + 1 < xcds && p >= n * (k + 1) / xcds) k++;
+    return k;
+}
+
+// The binning pass: a thread per pair (grid-stride), one atomic per run of
+// same-range queued lanes in a wave.
+__global__ __launch_bounds__(256) void k_bin(BatchArgs b, uint32_t tile) {
+    const FilterArgs &a = b.f;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t base = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); base < a.n_pairs;
+         base += stride) {
+        const uint64_t p = base + lane;
+        bool big = false;
+        if (p < a.n_pairs) {
+            const uint32_t r = a.r[p], s = a.s[p];
+            if ((r < a.n_r) & (s < a.n_s)) {
+                const uint32_t mr = uint32_t(max(a.Ar.off[r + 1] - a.Ar.off[r], a.Fr.off[r + 1] - a.Fr.off[r]));
+                const uint32_t ms = uint32_t(max(a.As.off[s + 1] - a.As.off[s], a.Fs.off[s + 1] - a.Fs.off[s]));
+                big = wg_bin(mr, ms, tile, b.wg_min);
+            }
+        }
+        const uint32_t k = p < a.n_pairs ? range_of(p, a.n_pairs, b.xcds) : 0u;
+        uint64_t todo = __ballot(big);
+        while (todo) {
+            // lanes of the first pending lane's range
+            const uint32_t k0 = uniform(__shfl(k, int(__builtin_ctzll(todo))));
+            const uint64_t mine = __ballot(big && k == k0) & todo;
+            todo &= ~mine;
+            unsigned int got = 0;
+            if (lane == uint32_t(__builtin_ctzll(mine)))
+                got = atomicAdd(&b.qfill[k0 * kCtrStride], uint32_t(__popcll(mine)));
+            got = __shfl(got, int(__builtin_ctzll(mine)));
+            if ((mine >> lane) & 1) {
+                const uint32_t slot = got + uint32_t(__popcll(mine & ((1ull << lane) - 1)));
+                if (slot < b.qcap) {
+                    b.queue[uint64_t(k0) * b.qcap + slot] = uint32_t(p);
+                    a.verdict[p] = kQueued;
+                } else {
+                    a.verdict[p] = kOverflow;
+                }
+            }
+        }
+    }
+}
 
 
 // ------------------------------------------------------------ join pieces
@@ -284,6 +368,50 @@ struct PairLists {
     uint32_t nxa, nxf, nya, nyf;
 };
 
+// Probe join, for a resident object X of few intervals spread over a wide
+// key range (its Hilbert key range crosses a large part of the curve) and a
+// long Y: streaming Y's elements in X's key window would read mostly
+// elements that fall in X's gaps.  Instead every lane takes one of X's
+// intervals from LDS and binary-searches Y in global memory with the same
+// formulation as the streamed join, roles swapped: X_t overlaps some Y_j iff
+// Y_{j*}.start < X_t.end, with j* the first j with Y_j.end > X_t.start.
+// Alg. 2's joins in its order: X.A in Y.A (AA); then X.A in Y.F and X.F in
+// Y.A (AF, FA).  Y.A is searched in its window [ja, jb) (elements ending
+// above X's first start and starting below X's last end: every overlap lies
+// there), Y.F whole.  Returns 0 = no AA overlap, 1 = a true hit, 2 = AA
+// overlaps only.
+__device__ __forceinline__ bool probe_any(const uint32_t *xs, const uint32_t *xe, uint32_t nx,
+                                          const uint32_t *__restrict__ ys, const uint32_t *__restrict__ ye,
+                                          uint32_t lo0, uint32_t hi0, uint32_t lane) {
+    for (uint32_t t0 = 0; t0 < nx; t0 += 64) {
+        const uint32_t t = t0 + lane;
+        const uint32_t key = t < nx ? xs[t] : 0u, end = t < nx ? xe[t] : 0u;
+        uint32_t lo = lo0, hi = t < nx ? hi0 : lo0;
+        while (__any(lo < hi)) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (lo < hi) {
+                if (gload(ye, m) > key) hi = m;
+                else lo = m + 1;
+            }
+        }
+        if (__any(t < nx && lo < hi0 && gload(ys, lo) < end)) return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ uint32_t probe_join(const Resident &x, const PairLists &L, uint32_t ja, uint32_t jb,
+                                               uint32_t lane) {
+    if (!probe_any(x.as, x.ae, x.na, L.yas, L.yae, ja, jb, lane)) return 0;
+    if (probe_any(x.as, x.ae, x.na, L.yfs, L.yfe, 0, L.nyf, lane)) return 1;
+    return probe_any(x.fs, x.fe, x.nf, L.yas, L.yae, ja, jb, lane) ? 1u : 2u;
+}
+
+// A single resident piece takes the probe join when its window in Y.A holds
+// more than this many elements per 64 resident intervals (a streamed chunk
+// of 128 elements costs about one memory round trip, a probe round about
+// eighteen dependent ones).
+constexpr uint32_t kProbeWindowPerRound = 2048;
+
 // Joins of one resident piece (key range [k0, k1)) with the streamed lists:
 // 0 = no AA overlap, 1 = a true hit (FA or AF overlap), 2 = AA overlap only.
 // Every value here is wave-uniform; uniform() says so to the compiler.
@@ -308,6 +436,15 @@ __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLi
     // a mapped end ((e - 1) >> sh) + 1 is above x_lo iff e is above x_lo << sh
     const uint32_t ja =
         (narrow || L.nya > search_min) ? uniform(wave_first_above(L.yae, L.nya, MAP == kShifted ? x_lo << sh : x_lo, lane)) : 0;
+    // (the 512-interval instance only: it has the registers to spare, and
+    // long objects, which a wide window needs, make the library pick it)
+    if (MODE == kAlg2 && TILE >= 512 && !narrow && k1 == kNone) {
+        const uint32_t rounds = (max(res.na, res.nf) + 63) / 64;
+        if (L.nya - ja > kProbeWindowPerRound * rounds) {
+            const uint32_t jb = ja + uniform(wave_first_above(L.yas + ja, L.nya - ja, x_hi - 1, lane));
+            if (jb - ja > kProbeWindowPerRound * rounds) return probe_join(res, L, ja, jb, lane);
+        }
+    }
     if (MODE == kWithinJoin) {
         const bool aa = (want & 1) && stream_piece<TILE, C, false, kAsIs>(res, L.yas, L.yae, ja, L.nya, x_hi, lane,
                                                                           &th, 0);
@@ -391,6 +528,176 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
     return aa ? APRIL_INDECISIVE : APRIL_TN;
 }
 
+// --------------------------------------------------- workgroup schedule
+//
+// A pair of two long objects (the workgroup bin) is joined by the four
+// waves of a workgroup together.  Their LDS holds one resident tile of
+// TW = 4 * TILE intervals per list (A.end, A.start, F.end, F.start, padded
+// with 0xFFFFFFFF as for a wave), so the shorter object X is cut into a
+// quarter as many pieces, and the waves split the streamed object Y: wave w
+// takes chunks w, w + 4, w + 8, ... of 64 * C elements.  An overlap raises
+// a flag in LDS; a true hit ends every wave's stream at its next chunk.
+//
+// Pieces are visited in key order, so the streamed lists are merged rather
+// than searched: piece k + 1 starts its stream where piece k's stopped.  A
+// wave stops at its first chunk that starts at or after the piece's end
+// (x_hi); with c* the smallest such chunk over the four waves, every chunk
+// before c* was streamed and started below x_hi, so every element before
+// chunk c* - 1 ends at or below x_hi, which is at most the next piece's
+// first key: the next piece restarts at chunk c* - 1.  (An element streamed
+// again, or one outside the piece's range, can only show a real overlap:
+// the LDS search compares it with real intervals of X.)
+
+struct WgShared {
+    uint32_t grab;      // queue entry taken by the workgroup
+    uint32_t bits;      // this pass: 1 = overlap with X.A, 2 = true hit
+    uint32_t cstop;     // this pass: smallest stop chunk over the waves
+    uint32_t pad;
+};
+
+constexpr uint32_t kHitAA = 1, kHitTH = 2;
+
+// One pass of the workgroup over Y[j0, m) against the resident tile, up to
+// the first chunk starting at or after `stop`.  FA: the pass over Y.A (an
+// A-list overlap sets kHitAA; one that also meets X.F sets kHitTH); else
+// the pass over Y.F (an overlap with X.A sets kHitTH).
+template <int TW, int C, bool FA>
+__device__ __forceinline__ void wg_stream(const Resident &x, const uint32_t *__restrict__ ys,
+                                          const uint32_t *__restrict__ ye, uint32_t j0, uint32_t m,
+                                          uint32_t stop, uint32_t w, uint32_t lane, WgShared *sh) {
+    uint32_t c = w;
+    for (;; c += kWavesPerBlock) {
+        const uint32_t j = j0 + c * (64 * C);
+        if (j >= m) break;
+        if (uniform(__hip_atomic_load(&sh->bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) & kHitTH) break;
+        uint32_t s[C], e[C];
+#pragma unroll
+        for (int q = 0; q < C; q++) {
+            const uint32_t k = j + q * 64 + lane;
+            s[q] = k < m ? gload(ys, k) : 0u;
+            e[q] = k < m ? gload(ye, k) : 0u;
+        }
+        if (uniform(s[0]) >= stop) break;
+        bool hit = false, f = false;
+#pragma unroll
+        for (int q = 0; q < C; q++) {
+            if (FA) {
+                const uint32_t *pa, *pf;
+                lds_first_above2<TW>(x.ae, x.fe, s[q], pa, pf);
+                const bool h = pa[TW] < e[q];
+                hit |= h;
+                f |= h & (pf[TW] < e[q]);
+            } else {
+                hit |= lds_first_above<TW>(x.ae, s[q])[TW] < e[q];
+            }
+        }
+        const bool any_hit = __any(hit);
+        const bool th = FA ? (any_hit && __any(f)) : any_hit;
+        if (any_hit && lane == 0)
+            __hip_atomic_fetch_or(&sh->bits, th ? (kHitAA | kHitTH) : kHitAA, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (th) break;
+    }
+    if (lane == 0) __hip_atomic_fetch_min(&sh->cstop, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Copy X's piece (na, nf < TW intervals) into the workgroup's tile: wave w
+// copies slots w * 64, (w + 4) * 64, ... and pads the rest.
+template <int TW>
+__device__ __forceinline__ void wg_load(const Resident &x, const uint32_t *__restrict__ as,
+                                        const uint32_t *__restrict__ ae, uint32_t na,
+                                        const uint32_t *__restrict__ fs, const uint32_t *__restrict__ fe,
+                                        uint32_t nf, uint32_t w, uint32_t lane) {
+#pragma unroll 1
+    for (uint32_t i = w; i < TW / 64; i += kWavesPerBlock) {
+        const uint32_t t = i * 64 + lane;
+        if (t < na) {
+            dma_dword(as + t, x.as + i * 64);
+            dma_dword(ae + t, x.ae + i * 64);
+        } else {
+            x.as[t] = 0xffffffffu;
+            x.ae[t] = 0xffffffffu;
+        }
+        if (t < nf) {
+            dma_dword(fs + t, x.fs + i * 64);
+            dma_dword(fe + t, x.fe + i * 64);
+        } else {
+            x.fs[t] = 0xffffffffu;
+            x.fe[t] = 0xffffffffu;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+// Alg. 2's verdict for one workgroup-bin pair, by the whole workgroup.
+// Every value that steers control flow is the same in all four waves (the
+// same scalar loads, or LDS words read after a barrier), so every wave
+// reaches every barrier.
+template <int TW, int C>
+__device__ uint32_t wg_pair(const Resident &res, const PairLists &L, uint32_t search_min, uint32_t w,
+                            uint32_t lane, WgShared *sh) {
+    bool aa = false;
+    uint32_t a0 = 0, f0 = 0, k0 = 0;
+    uint32_t ja = kNone, jf = kNone;   // stream restart points (kNone: search first)
+    bool jf_tight = false;             // jf was set by the previous piece's F pass
+    for (;;) {
+        uint32_t a1 = L.nxa, f1 = L.nxf, k1 = kNone;
+        if (L.nxa - a0 > TW - 1) {
+            a1 = a0 + TW - 1;
+            k1 = uniform(gload(L.xas, a1));
+            f1 = f0 + uniform(wave_first_above(L.xfs + f0, L.nxf - f0, k1 - 1, lane));
+        }
+        if (f1 - f0 > TW - 1) {
+            f1 = f0 + TW - 1;
+            k1 = uniform(gload(L.xfs, f1));
+            a1 = a0 + uniform(wave_first_above(L.xas + a0, a1 - a0, k1 - 1, lane));
+        }
+        __syncthreads();   // every wave is done with the previous piece's tile and flags
+        if (w == 0 && lane == 0) {
+            sh->bits = 0;
+            sh->cstop = kNone;
+        }
+        wg_load<TW>(res, L.xas + a0, L.xae + a0, a1 - a0, L.xfs + f0, L.xfe + f0, f1 - f0, w, lane);
+        __syncthreads();   // the tile and the cleared flags are in place
+        const uint32_t na = a1 - a0;
+        const uint32_t x_lo = max(k0, uniform(res.as[0]));
+        const uint32_t x_hi = min(k1, uniform(res.ae[na - 1]));
+        if (ja == kNone)
+            ja = L.nya > search_min ? uniform(wave_first_above(L.yae, L.nya, x_lo, lane)) : 0u;
+        wg_stream<TW, C, true>(res, L.yas, L.yae, ja, L.nya, x_hi, w, lane, sh);
+        __syncthreads();
+        uint32_t bits = uniform(sh->bits);
+        uint32_t cs = uniform(sh->cstop);
+        if (bits & kHitTH) return APRIL_TH;
+        ja = ja + (cs > 0 ? (cs - 1) * (64 * C) : 0u);
+        if (bits & kHitAA) {
+            aa = true;
+            // AF: Y.F against X.A over the same key range
+            if (!jf_tight) {
+                const uint32_t from = jf == kNone ? 0u : jf;
+                jf = from + uniform(wave_first_above(L.yfe + from, L.nyf - from, x_lo, lane));
+            }
+            __syncthreads();   // every wave has read the flags of the A pass
+            if (w == 0 && lane == 0) sh->cstop = kNone;
+            __syncthreads();
+            wg_stream<TW, C, false>(res, L.yfs, L.yfe, jf, L.nyf, x_hi, w, lane, sh);
+            __syncthreads();
+            bits = uniform(sh->bits);
+            cs = uniform(sh->cstop);
+            if (bits & kHitTH) return APRIL_TH;
+            jf = jf + (cs > 0 ? (cs - 1) * (64 * C) : 0u);
+            jf_tight = true;
+        } else {
+            jf_tight = false;
+        }
+        if (k1 == kNone) break;
+        k0 = k1;
+        a0 = uniform(gload(L.xae, a1 - 1)) > k1 ? a1 - 1 : a1;
+        f0 = (f1 > 0 && uniform(gload(L.xfe, f1 - 1)) > k1) ? f1 - 1 : f1;
+    }
+    return aa ? APRIL_INDECISIVE : APRIL_TN;
+}
+
 // ------------------------------------------------------------- persistent
 
 __device__ __forceinline__ uint64_t join64(uint32_t lo, uint32_t hi) { return (uint64_t(hi) << 32) | lo; }
@@ -429,6 +736,85 @@ __device__ __forceinline__ PairLists lane_pair(const PairLists &m, uint32_t k) {
     return L;
 }
 
+// The end of a wave of a persistent kernel, for APRIL_WAVE_TIMES: t[0] and
+// t[1] take the earliest and the latest end (the call's start is taken by
+// the zeroing kernel that precedes the launches).  Lane 0 only.
+__device__ __forceinline__ void wave_ended(unsigned long long *t) {
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    atomicMin(&t[0], now);
+    atomicMax(&t[1], now);
+}
+
+// The workgroup bin: a persistent kernel whose workgroups take the queued
+// pairs, each XCD's workgroups from that XCD range's queue first, then the
+// others'.  It runs before the wave kernel (same stream), so the longest
+// joins start first.
+template <int TILE, int C>
+__global__ __launch_bounds__(kBlock) void k_wg(BatchArgs b) {
+    __shared__ uint32_t lds_words[kWavesPerBlock * 4 * TILE];
+    __shared__ WgShared wg_sh;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t w = uniform(threadIdx.x >> 6);
+    unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
+    const uint32_t xcds = b.xcds;
+    const uint32_t my_xcd = blockIdx.x % xcds;
+    {
+        constexpr int TW = kWavesPerBlock * TILE;
+        Resident wres;
+        wres.ae = lds_words;   // one tile of TW per list: A.end, A.start, F.end, F.start
+        wres.as = wres.ae + TW;
+        wres.fe = wres.as + TW;
+        wres.fs = wres.fe + TW;
+        wres.na = wres.nf = 0;
+        for (uint32_t k = 0; k < xcds; k++) {
+            typedef const __attribute__((address_space(4))) BatchArgs *KArgs;
+            KArgs pb = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+            asm volatile("" : "+s"(pb));
+            const uint32_t seg = (my_xcd + k) % xcds;
+            // (every wave reads the same count: the binning pass has ended;
+            // the grab is one thread's, passed on through LDS, so that all
+            // four waves take the same branches and reach every barrier)
+            const uint32_t nq = uniform(min(pb->qfill[seg * kCtrStride], pb->qcap));
+            for (;;) {
+                __syncthreads();   // the last pair's shared words are no longer read
+                if (threadIdx.x == 0) wg_sh.grab = atomicAdd(&pb->qhead[seg * kCtrStride], 1u);
+                __syncthreads();
+                const uint32_t q = uniform(wg_sh.grab);
+                if (q >= nq) break;
+                const __attribute__((address_space(4))) FilterArgs &a = pb->f;
+                const uint64_t p = pb->queue[uint64_t(seg) * pb->qcap + q];
+                const uint32_t r = uniform(gload32(a.r, p)), s = uniform(gload32(a.s, p));
+                const uint64_t ar0 = gload64(a.Ar.off, r), fr0 = gload64(a.Fr.off, r);
+                const uint64_t as0 = gload64(a.As.off, s), fs0 = gload64(a.Fs.off, s);
+                const uint32_t nar = uint32_t(gload64(a.Ar.off, r + 1) - ar0);
+                const uint32_t nfr = uint32_t(gload64(a.Fr.off, r + 1) - fr0);
+                const uint32_t nas = uint32_t(gload64(a.As.off, s + 1) - as0);
+                const uint32_t nfs = uint32_t(gload64(a.Fs.off, s + 1) - fs0);
+                const bool xs = max(nas, nfs) < max(nar, nfr);   // the shorter object is cut into pieces
+                const PairLists L = pair_lists(a, xs, ar0, nar, fr0, nfr, as0, nas, fs0, nfs);
+                const uint32_t v = wg_pair<TW, C>(wres, L, pb->search_min, w, lane, &wg_sh);
+                if (threadIdx.x == 0) {
+                    pb->f.verdict[p] = uint8_t(v);
+                    c_tn += v == APRIL_TN;
+                    c_th += v == APRIL_TH;
+                    c_ind += v == APRIL_INDECISIVE;
+                }
+            }
+        }
+        __syncthreads();   // the shared tile is free for the waves' own tiles
+    }
+    if (b.f.counts) {
+        for (int off = 32; off > 0; off >>= 1) {
+            c_tn += __shfl_down(c_tn, off);
+            c_th += __shfl_down(c_th, off);
+            c_ind += __shfl_down(c_ind, off);
+        }
+        const unsigned long long v[3] = {c_tn, c_th, c_ind};
+        if (lane == 0) add_totals(b.xhead, blockIdx.x * kWavesPerBlock + w, v, 3);
+    }
+    if (b.times && lane == 0) wave_ended(b.times + 3);
+}
+
 template <int TILE, int C, int MODE>
 // Register budget: 8 waves per SIMD where LDS allows it (TILE <= 256).
 // The hardware allocates SGPRs in blocks of 16, and above 80 SGPRs fewer
@@ -441,6 +827,10 @@ void k_batched(BatchArgs b) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t w = uniform(threadIdx.x >> 6);
     unsigned long long c_tn = 0, c_th = 0, c_ind = 0;
+    const uint32_t xcds = b.xcds;
+    const uint32_t my_xcd = blockIdx.x % xcds;
+
+
     Resident res;
     res.ae = lds_words + w * 4 * TILE;   // layout: A.end, A.start, F.end, F.start
     res.as = res.ae + TILE;
@@ -451,8 +841,6 @@ void k_batched(BatchArgs b) {
 
     // ---- pairs in input order: each XCD drains its own contiguous range,
     // then helps the others
-    const uint32_t xcds = b.xcds;
-    const uint32_t my_xcd = blockIdx.x % xcds;
     uint32_t grab = b.grab;
     for (uint32_t k = 0; k < xcds; k++) {
         const uint32_t seg = (my_xcd + k) % xcds;
@@ -485,6 +873,7 @@ void k_batched(BatchArgs b) {
             // lane k's pair: its lists with X the object to keep resident
             PairLists m{};
             uint32_t key = kNone;
+            bool mine = p < g1;   // false for a pair the workgroup bin answers
             if (p < g1) {
                 const uint32_t r = gload32(a.r, p), s = gload32(a.s, p);
                 if ((r < a.n_r) & (s < a.n_s)) {
@@ -495,6 +884,9 @@ void k_batched(BatchArgs b) {
                     const uint32_t nas = uint32_t(gload64(a.As.off, s + 1) - as0);
                     const uint32_t nfs = uint32_t(gload64(a.Fs.off, s + 1) - fs0);
                     const uint32_t mr = max(nar, nfr), ms = max(nas, nfs);
+                    if (MODE == kAlg2 && wg_bin(mr, ms, TILE, pb->wg_min) &&
+                        ((const uint8_t __attribute__((address_space(1))) *)a.verdict)[p] != kOverflow)
+                        mine = false;
                     // R resident when its lists fit a tile; else S when its
                     // do or when neither does and S's are shorter
                     // (mixed orders: the coarser side, whose lists stay
@@ -504,7 +896,8 @@ void k_batched(BatchArgs b) {
                                     : MODE == kWithinJoin ? true
                                     : MODE == kLinestrings ? false
                                                            : !(mr < TILE) && (ms < TILE || ms < mr);
-                    if (MODE == kAlg2 && max(mr, ms) <= pb->thread_max) seq = true;
+                    if (!mine) {
+                    } else if (MODE == kAlg2 && max(mr, ms) <= pb->thread_max) seq = true;
                     else wave = true;
                     m = pair_lists(a, xs, ar0, nar, fr0, nfr, as0, nas, fs0, nfs);
                     key = (xs ? s : r) | (xs ? kSideS : 0u);
@@ -537,7 +930,7 @@ void k_batched(BatchArgs b) {
                     v = APRIL_INDECISIVE;
                 vv = v;
             }
-            if (p < g1) {
+            if (mine) {
                 pb->f.verdict[p] = uint8_t(vv);
                 c_tn += vv == APRIL_TN;
                 c_th += vv == APRIL_TH;
@@ -555,6 +948,7 @@ void k_batched(BatchArgs b) {
         const unsigned long long v[3] = {c_tn, c_th, c_ind};
         if (lane == 0) add_totals(b.xhead, blockIdx.x * kWavesPerBlock + w, v, 3);
     }
+    if (b.times && lane == 0) wave_ended(b.times + 1);
 }
 
 
@@ -574,6 +968,19 @@ int launch_tc(const BatchArgs &b, int cus, uint32_t waves, hipStream_t stream) {
     // a range is near its end once its waves have about two full grabs each left
     BatchArgs bb = b;
     bb.tail_pairs = 2ull * b.grab * kWavesPerBlock * ((blocks + b.xcds - 1) / b.xcds);
+    if (MODE == kAlg2 && b.wg_min != kNone) {
+        const uint64_t bin_blocks = std::min<uint64_t>((b.f.n_pairs + 255) / 256, uint64_t(cus) * 8);
+        k_bin<<<dim3(uint32_t(bin_blocks)), dim3(256), 0, stream>>>(bb, TILE);
+        APRIL_HIP_TRY(hipGetLastError());
+        static int wg_per_cu = 0;   // resident workgroups per CU
+        if (!wg_per_cu) {
+            int q = 0;
+            APRIL_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k_wg<TILE, C>, kBlock, 0));
+            wg_per_cu = q < 1 ? 1 : q;
+        }
+        k_wg<TILE, C><<<dim3(uint32_t(uint64_t(cus) * wg_per_cu)), dim3(kBlock), 0, stream>>>(bb);
+        APRIL_HIP_TRY(hipGetLastError());
+    }
     k_batched<TILE, C, MODE><<<dim3(uint32_t(blocks)), dim3(kBlock), 0, stream>>>(bb);
     APRIL_HIP_TRY(hipGetLastError());
     if (b.f.counts) {
@@ -595,9 +1002,35 @@ int launch_t(const BatchArgs &b, uint32_t chunk, int cus, uint32_t waves, hipStr
 
 }  // namespace
 
-uint64_t batched_workspace_bytes(uint64_t) { return kCtrBytes; }
+// Workspace of the batched schedule: the counters and count slots
+// (kCtrBytes), the workgroup queues' fill and head counters (two regions of
+// kMaxCtrs slots, 128 bytes apart), then the queues: kBigQueueCap pair
+// indices shared evenly by the XCD ranges.
+constexpr uint64_t kQueueCtrBytes = 2ull * kMaxCtrs * kCtrStride * sizeof(unsigned int);
+static_assert(kCtrBytes + kQueueCtrBytes + 4ull * kBigQueueCap <= kStaticWorkspaceBytes,
+              "the static scratch holds a batched workspace");
 
-int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? std::min<int>(cus / 32, kMaxCtrs) : 1; }
+uint64_t batched_workspace_bytes(uint64_t) { return kCtrBytes + kQueueCtrBytes + 4ull * kBigQueueCap; }
+
+// Wave times (APRIL_WAVE_TIMES) sit in the last fill-counter slot, which no
+// XCD range uses (xcd_count stays below kMaxCtrs).
+constexpr uint64_t kTimesOffset = kCtrBytes + uint64_t(kMaxCtrs - 1) * kCtrStride * sizeof(unsigned int);
+static_assert(kTimesOffset == APRIL_WAVE_TIMES_OFFSET, "wave times offset");
+
+__global__ void k_zero_queue_ctrs(unsigned int *qctr) {
+    const uint32_t t = threadIdx.x;
+    if (t < 2 * kMaxCtrs && t != kMaxCtrs - 1) qctr[t * kCtrStride] = 0;
+    if (t == kMaxCtrs - 1) {
+        // the launch's start (the kernels that follow on the stream begin
+        // after this one), then the two end times
+        unsigned long long *times = reinterpret_cast<unsigned long long *>(qctr + (kMaxCtrs - 1) * kCtrStride);
+        times[0] = __builtin_amdgcn_s_memrealtime();
+        times[1] = times[3] = ~0ull;
+        times[2] = times[4] = 0;
+    }
+}
+
+int xcd_count(int cus) { return (cus >= 64 && cus % 32 == 0) ? std::min<int>(cus / 32, kMaxCtrs - 1) : 1; }
 
 __global__ void k_zero_ctrs(unsigned int *ctr) {
     const uint32_t t = threadIdx.x;
@@ -619,6 +1052,18 @@ __global__ void k_sum_totals(const unsigned int *ctr, unsigned long long *totals
     }
 }
 
+// Workgroup-bin fields of the arguments: off (kNone) or on, with the queues
+// in the workspace after the counters.
+static void set_wg_bin(BatchArgs &b, uint32_t wg_min, void *workspace) {
+    unsigned int *qctr = reinterpret_cast<unsigned int *>(static_cast<char *>(workspace) + kCtrBytes);
+    b.wg_min = wg_min;
+    b.qfill = qctr;
+    b.qhead = qctr + kMaxCtrs * kCtrStride;
+    b.queue = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + kCtrBytes + kQueueCtrBytes);
+    b.qcap = uint32_t(kBigQueueCap / b.xcds);
+    b.times = nullptr;
+}
+
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
                    hipStream_t stream) {
     const uint32_t tile = o.tile ? o.tile : 256;
@@ -629,6 +1074,12 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     b.xcds = uint32_t(xcd_count(cus));
     b.thread_max = o.thread_max ? o.thread_max : 8;
     b.search_min = o.search_min ? o.search_min : 512;
+    // workgroup bin: pairs whose shorter object spans kDefaultWgMin
+    // intervals or more (0 = that default, 0xFFFFFFFF = no workgroup bin);
+    // pair indices in the queues are 32-bit
+    uint32_t wg_min = o.wg_min ? o.wg_min : kDefaultWgMin;
+    if (a.n_pairs >= (1ull << 32)) wg_min = kNone;
+    set_wg_bin(b, wg_min, workspace);
     // Grabs of 32 pairs: an XCD's waves then hold about 32k consecutive
     // pairs at once, whose S objects' lists about fill its L2 (4 MB); with
     // 64 the at-scale join ran 4% slower (2.13 vs 2.05 ms), with 16 no faster.
@@ -638,6 +1089,12 @@ int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, v
     if (b.thread_max >= tile) return fail(APRIL_E_INVALID, "thread_max must be below tile");
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
+    if (o.flags & APRIL_WAVE_TIMES)
+        b.times = reinterpret_cast<unsigned long long *>(static_cast<char *>(workspace) + kTimesOffset);
+    if (wg_min != kNone || b.times) {
+        k_zero_queue_ctrs<<<1, 2 * kMaxCtrs, 0, stream>>>(b.qfill);
+        APRIL_HIP_TRY(hipGetLastError());
+    }
     switch (tile) {
         case 128: return launch_t<128>(b, chunk, cus, o.waves, stream);
         case 256: return launch_t<256>(b, chunk, cus, o.waves, stream);
@@ -659,6 +1116,7 @@ int launch_batched_mixed(const FilterArgs &a, uint32_t shift_r, uint32_t shift_s
     b.tail_grab = 8;
     b.shift_r = shift_r;
     b.shift_s = shift_s;
+    set_wg_bin(b, kNone, workspace);
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     return launch_tc<256, 2, kMixedOrders>(b, cus, 0, stream);
@@ -674,6 +1132,7 @@ int launch_batched_within(const FilterArgs &a, int cus, void *workspace, hipStre
     b.grab = 32;
     b.tail_grab = 8;
     b.shift_r = b.shift_s = 0;
+    set_wg_bin(b, kNone, workspace);
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     return launch_tc<256, 2, kWithinJoin>(b, cus, 0, stream);
@@ -689,6 +1148,7 @@ int launch_batched_linestrings(const FilterArgs &a, int cus, void *workspace, hi
     b.grab = 32;
     b.tail_grab = 8;
     b.shift_r = b.shift_s = 0;
+    set_wg_bin(b, kNone, workspace);
     k_zero_ctrs<<<1, 64, 0, stream>>>(b.xhead);
     APRIL_HIP_TRY(hipGetLastError());
     return launch_tc<256, 2, kLinestrings>(b, cus, 0, stream);

@@ -52,9 +52,18 @@ constexpr uint32_t kCtrStride = 32;    // uint32 words per slot
 constexpr uint32_t kMaxCtrs = 64;
 constexpr uint32_t kSlotWords = 16;    // uint64 words per slot
 constexpr uint64_t kCtrBytes = 2ull * kMaxCtrs * kCtrStride * sizeof(unsigned int);
+// Pairs the batched schedule can queue for its workgroup bin in one call
+// (the rest of that bin runs on single waves).
+constexpr uint64_t kBigQueueCap = 1ull << 20;
+// Default workgroup-bin threshold: pairs whose shorter object spans at
+// least this many intervals (and neither object fits a tile) run on a
+// workgroup.  On the skewed workload 2048 and 4096 time the same; on the
+// at-scale one (longest list 3,588 intervals) 4096 leaves the bin empty, so
+// the binning pass is skipped.
+constexpr uint32_t kDefaultWgMin = 4096;
 // Workspace part of the static scratch (april_filter_pairs_static): enough
 // for any filter call's scratch on raw lists.
-constexpr uint64_t kStaticWorkspaceBytes = 64ull << 10;
+constexpr uint64_t kStaticWorkspaceBytes = (4ull << 20) + (64ull << 10);
 
 // zero both regions
 __global__ void k_zero_ctrs(unsigned int *ctr);

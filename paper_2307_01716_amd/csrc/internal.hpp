@@ -63,6 +63,10 @@ struct april_lists {
     uint64_t n = 0, n_a = 0, n_f = 0;
     int device = -1;                 // -1: host lists
     uint32_t codec = APRIL_CODEC_RAW;
+    // device lists uploaded from host lists: the most intervals in one
+    // object's A- or F-list (0xffffffff: not known), which tells the filter
+    // whether any pair can reach its workgroup bin
+    uint32_t max_len = 0xffffffffu;
     // host copy (empty for device lists)
     std::vector<uint64_t> off_a, off_f;
     std::vector<uint32_t> start_a, end_a, start_f, end_f;

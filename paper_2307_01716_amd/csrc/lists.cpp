@@ -253,6 +253,10 @@ int april_lists_to_device(const april_lists_t *h, uint32_t codec, void *stream,
     L->n = h->n; L->n_a = h->n_a; L->n_f = h->n_f;
     L->device = dev;
     L->codec = codec;
+    uint64_t longest = 0;
+    for (uint64_t k = 0; k < h->n; k++)
+        longest = std::max({longest, h->off_a[k + 1] - h->off_a[k], h->off_f[k + 1] - h->off_f[k]});
+    L->max_len = uint32_t(std::min<uint64_t>(longest, 0xfffffffeull));
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const uint64_t n = h->n;
     const size_t b_off = up(8 * (n + 1));

@@ -108,10 +108,11 @@ def _per_kernel(pmc_dir: str, counter: str, kernel: str):
     return got
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int = 1 << 30):
+def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int = 1 << 30, parts=None):
     """HBM bytes per launch of `kernel` from FETCH_SIZE / WRITE_SIZE runs, each
     scaled by the counter's reading for a copy of `copy_bytes` (which reads
-    and writes copy_bytes)."""
+    and writes copy_bytes).  With `parts` (kernel name prefixes), a launch is
+    one dispatch of each, and their per-dispatch averages are summed."""
     kib = copy_bytes / 1024.0
     cf = _per_kernel(fetch_dir, "FETCH_SIZE", COPY_KERNEL)
     cw = _per_kernel(write_dir, "WRITE_SIZE", COPY_KERNEL)
@@ -120,15 +121,27 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int = 1 << 
     cw = [x for x in cw if x > kib / 8]
     f_factor = kib / (sum(cf) / len(cf))
     w_factor = kib / (sum(cw) / len(cw))
-    kf = _per_kernel(fetch_dir, "FETCH_SIZE", kernel)
-    kw = _per_kernel(write_dir, "WRITE_SIZE", kernel)
-    fetch = sum(kf) / len(kf) * 1024.0 * f_factor
-    write = sum(kw) / len(kw) * 1024.0 * w_factor
-    return {"fetch_kib_raw": sum(kf) / len(kf), "write_kib_raw": sum(kw) / len(kw),
-            "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw),
-            "fetch_factor": f_factor, "write_factor": w_factor,
-            "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
-            "dispatches": len(kf)}
+    fk = wk = 0.0
+    per_part = {}
+    n = None
+    for part in parts or [kernel]:
+        kf = _per_kernel(fetch_dir, "FETCH_SIZE", part)
+        kw = _per_kernel(write_dir, "WRITE_SIZE", part)
+        per_part[part] = {"fetch_kib_raw": sum(kf) / len(kf), "write_kib_raw": sum(kw) / len(kw),
+                          "dispatches": len(kf)}
+        fk += sum(kf) / len(kf)
+        wk += sum(kw) / len(kw)
+        n = len(kf) if n is None else min(n, len(kf))
+    fetch = fk * 1024.0 * f_factor
+    write = wk * 1024.0 * w_factor
+    out = {"fetch_kib_raw": fk, "write_kib_raw": wk,
+           "copy_fetch_kib": sum(cf) / len(cf), "copy_write_kib": sum(cw) / len(cw),
+           "fetch_factor": f_factor, "write_factor": w_factor,
+           "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
+           "dispatches": n}
+    if parts:
+        out["parts"] = per_part
+    return out
 
 
 def read_traffic(path: str, kernel: str, config: dict, pairs: int):
@@ -154,6 +167,8 @@ def main():
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
     t.add_argument("--kernel", default="k_batched")
+    t.add_argument("--parts", default="", help="kernel name prefixes of one launch, comma-separated "
+                                               "(default: the kernel alone)")
     t.add_argument("--config", default="")
     t.add_argument("--pairs", type=int, required=True)
     t.add_argument("--alg-bytes", type=int, default=0)
@@ -175,7 +190,8 @@ def main():
                           " ".join(f"{k}={x:.6g}" for k, x in sorted(v.items())))
     else:
         cfg = {k: int(v) for k, v in (kv.split("=") for kv in args.config.split(","))} if args.config else {}
-        tr = traffic(args.fetch, args.write, args.kernel)
+        tr = traffic(args.fetch, args.write, args.kernel,
+                     parts=[p for p in args.parts.split(",") if p] or None)
         rec = {"kernel": args.kernel, "config": cfg, "pairs": args.pairs, "alg_bytes": args.alg_bytes,
                "source_sha256": source_digest(args.kernel), "traffic": tr, "command": args.command}
         with open(args.out, "w") as f:

@@ -66,7 +66,7 @@ GRID = (0.0, 0.0, float(1 << 16) * 2.0 ** -30 * (1 << 16), 16)
 # schedules under test: plain, batched with defaults, and batched tunings
 # that push pairs through every bin and code path (lane-per-pair bin, wave
 # bin with either side resident, big pairs with the resident lists cut into
-# pieces, range search on every streamed list)
+# pieces on one wave or on a workgroup, range search on every streamed list)
 SCHEDULES = {
     "plain": dict(schedule=april.SCHED_PLAIN),
     "batched": dict(schedule=april.SCHED_BATCHED),
@@ -74,6 +74,11 @@ SCHEDULES = {
                                 search_min=64),
     "batched-wide": dict(schedule=april.SCHED_BATCHED, tile=512, chunk=4, thread_max=1,
                          search_min=1),
+    # every pair in which neither object fits a tile runs on a workgroup
+    "batched-workgroup": dict(schedule=april.SCHED_BATCHED, tile=128, chunk=1, wg_min=1,
+                              search_min=64),
+    # no workgroup bin: such pairs run on one wave, piece by piece
+    "batched-no-workgroup": dict(schedule=april.SCHED_BATCHED, tile=128, wg_min=0xFFFFFFFF),
 }
 
 

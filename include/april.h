@@ -342,7 +342,10 @@ int april_filter_pairs_static(const april_lists_t *R, const april_lists_t *S, co
  * AA -> AF -> FA merge-joins with early exit must read and write.
  * d_bytes[p] (device uint64[n_pairs]) = 8 (the pair's two uint32 ids)
  *   + 16 per list whose CSR bounds Alg. 2 reads (two uint64 offsets)
- *   + 8 per distinct interval it reads (two uint32 endpoints)
+ *   + 8 per distinct interval it reads (two uint32 endpoints), or, for
+ *     compressed lists (Sec. 5.1), the bytes of each list's prefix that
+ *     decoding those intervals consumes (Alg. 2 reads every list from its
+ *     start, so no block-index entry)
  *   + 1 (the verdict); 0 for an out-of-range pair.
  * Summed over a batch this is the "algorithmic bytes" of the filter.
  * Computed on the device, one lane per pair; asynchronous on hip_stream.

@@ -1052,6 +1052,20 @@ __global__ void k_sum_totals(const unsigned int *ctr, unsigned long long *totals
     }
 }
 
+void batched_defaults(april_filter_opts_t &o, const BatchedShape &shape) {
+    // default tile: 256 intervals when a typical A-list fits it (more waves
+    // per CU), else 512 (fewer pieces, and the probe join for short objects
+    // spread over a wide key range).  Measured: 6% faster at 256 on the
+    // at-scale join (mean 177 intervals); 11% faster at 512 on the skewed
+    // one (mean 990; 75.7 against 84.9 ms).
+    if (!o.tile) o.tile = shape.intervals_a <= 256 * shape.objects ? 256 : 512;
+    // the workgroup bin needs two objects of at least max(tile, wg_min)
+    // intervals: without such objects on both sides, no binning pass
+    if (!o.wg_min) o.wg_min = kDefaultWgMin;
+    const uint64_t need_len = std::max(o.tile, o.wg_min);
+    if (shape.max_len_r < need_len || shape.max_len_s < need_len) o.wg_min = kNone;
+}
+
 // Workgroup-bin fields of the arguments: off (kNone) or on, with the queues
 // in the workspace after the counters.
 static void set_wg_bin(BatchArgs &b, uint32_t wg_min, void *workspace) {

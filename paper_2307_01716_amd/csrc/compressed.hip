@@ -278,6 +278,86 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
 }
 
 
+// Alg. 2's data movement on compressed lists, one lane per pair: the joins
+// run sequentially as in Alg. 2 (AA; then AF, then FA), each list decoded
+// value by value from its start, and the bytes of each list's consumed
+// prefix are counted (the longest prefix over the joins that read it).
+struct SeqReader {
+    const uint8_t *p;
+    uint32_t prev;   // last value decoded
+    uint32_t left;   // intervals not yet decoded
+    uint64_t used;   // bytes consumed
+    uint32_t s, e;   // current interval
+};
+
+__device__ __forceinline__ uint32_t seq_value(SeqReader &c) {
+    uint32_t d = 0, sh = 0, b;
+    do {
+        b = *c.p++;
+        d |= (b & 0x7fu) << sh;
+        sh += 7;
+        c.used++;
+    } while (b & 0x80u);
+    c.prev = c.prev + d + 1u;
+    return c.prev;
+}
+
+__device__ __forceinline__ bool seq_next(SeqReader &c) {
+    if (!c.left) return false;
+    c.left--;
+    c.s = seq_value(c);
+    c.e = seq_value(c);
+    return true;
+}
+
+__device__ __forceinline__ SeqReader seq_open(const CList &L, uint32_t k) {
+    SeqReader c;
+    c.p = L.bytes + L.boff[k];
+    c.prev = 0xffffffffu;
+    c.left = uint32_t(L.off[k + 1] - L.off[k]);
+    c.used = 0;
+    c.s = c.e = 0;
+    return c;
+}
+
+// IntervalJoin of Alg. 2 on two compressed lists; *bx, *by: bytes of each
+// list consumed (the elements read, decoded in order).
+__device__ bool seq_join_vbyte(const CList &X, uint32_t kx, const CList &Y, uint32_t ky, uint64_t *bx,
+                               uint64_t *by) {
+    SeqReader x = seq_open(X, kx), y = seq_open(Y, ky);
+    bool found = false;
+    if (seq_next(x) && seq_next(y)) {
+        for (;;) {
+            if (x.s < y.e && y.s < x.e) { found = true; break; }
+            if (x.e <= y.e) { if (!seq_next(x)) break; }
+            else if (!seq_next(y)) break;
+        }
+    }
+    *bx = x.used;
+    *by = y.used;
+    return found;
+}
+
+__global__ void k_alg2_vbyte_bytes(CArgs a, unsigned long long *bytes) {
+    for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < a.n_pairs;
+         p += uint64_t(gridDim.x) * blockDim.x) {
+        const uint32_t r = a.r[p], s = a.s[p];
+        if (r >= a.n_r || s >= a.n_s) { bytes[p] = 0; continue; }
+        uint64_t bar, bas, bfr = 0, bfs = 0, x, y, lists = 2;
+        if (seq_join_vbyte(a.Ar, r, a.As, s, &bar, &bas)) {
+            lists++;
+            const bool af = seq_join_vbyte(a.Ar, r, a.Fs, s, &x, &bfs);
+            bar = max(bar, x);
+            if (!af) {
+                lists++;
+                seq_join_vbyte(a.Fr, r, a.As, s, &bfr, &y);
+                bas = max(bas, y);
+            }
+        }
+        bytes[p] = 8ull + 16ull * lists + bar + bas + bfr + bfs + 1ull;
+    }
+}
+
 // One wave per list: decode it whole into raw start/end arrays.
 __global__ __launch_bounds__(256) void k_decode_lists(const uint8_t *bytes, const uint64_t *boff,
                                                       const uint64_t *off, uint64_t n, uint32_t *out_s,
@@ -385,6 +465,25 @@ int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const ui
         k_sum_totals<<<1, 64, 0, stream>>>(a.xhead, counts, 3);
         APRIL_HIP_TRY(hipGetLastError());
     }
+    return APRIL_OK;
+}
+
+int launch_alg2_vbyte_bytes(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                            const uint32_t *d_s, uint64_t n_pairs, unsigned long long *d_bytes, int cus,
+                            hipStream_t stream) {
+    CArgs a{};
+    a.Ar = clist(R, false);
+    a.Fr = clist(R, true);
+    a.As = clist(S, false);
+    a.Fs = clist(S, true);
+    a.r = d_r;
+    a.s = d_s;
+    a.n_pairs = n_pairs;
+    a.n_r = R->n;
+    a.n_s = S->n;
+    const uint64_t blocks = std::min<uint64_t>((n_pairs + 255) / 256, uint64_t(cus) * 16);
+    k_alg2_vbyte_bytes<<<dim3(uint32_t(blocks)), dim3(256), 0, stream>>>(a, d_bytes);
+    APRIL_HIP_TRY(hipGetLastError());
     return APRIL_OK;
 }
 

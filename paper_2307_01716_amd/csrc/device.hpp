@@ -111,9 +111,16 @@ __device__ inline bool seq_join(const uint32_t *__restrict__ xs, const uint32_t 
 }
 
 
-// Batched schedule (batched.hip): scratch bytes for n_pairs, and the launch
-// of its binning and persistent kernels on `workspace`.
+// Batched schedule (batched.hip): scratch bytes for n_pairs, the library's
+// default settings for a call (filled into the zero fields of `o`), and the
+// launch of its binning and persistent kernels on `workspace`.
 uint64_t batched_workspace_bytes(uint64_t n_pairs);
+struct BatchedShape {
+    uint64_t intervals_a;   // A-list intervals of both collections
+    uint64_t objects;       // objects of both collections
+    uint32_t max_len_r, max_len_s;   // longest list of one object (0xffffffff: unknown)
+};
+void batched_defaults(april_filter_opts_t &o, const BatchedShape &shape);
 // XCDs of a device with `cus` compute units (32 CUs each on gfx950)
 int xcd_count(int cus);
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,

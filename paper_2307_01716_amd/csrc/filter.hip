@@ -42,51 +42,79 @@ static __device__ __align__(256) unsigned char scratch[april::kStaticScratchByte
 namespace april {
 namespace {
 
+// One wave's LDS tiles: the two lists' starts and ends, each its own array
+// of 64*K words at t, t + 64K, t + 128K, t + 192K (X starts, X ends, Y starts,
+// Y ends).  A lane's merge-path search reads ends only, so these reads fall
+// on consecutive words rather than every other word of interleaved
+// (start, end) pairs: LDS bank conflicts per LDS instruction fell from 2.5
+// to about 0.9 at scale, and the kernel from 6.07 to 5.83 ms.  (Padding one word
+// per 64, against the remaining two-way conflicts of lanes two elements
+// apart, and a first tile of 64 intervals, against loads past an early
+// overlap, each made it slower: 6.32 and 6.49 ms.)
+
+// One tile of the merge: both lists' next 64*K intervals from (i0, j0) are
+// staged in LDS, every lane runs K steps of Alg. 2's loop from its
+// diagonal's merge-path point; true iff some lane saw an overlap, else
+// (i0, j0) advance to the tile's last diagonal.
+template <int K>
+__device__ __forceinline__ bool merge_tile(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
+                                           uint32_t n, const uint32_t *__restrict__ ys,
+                                           const uint32_t *__restrict__ ye, uint32_t m, uint32_t *t,
+                                           uint32_t &i0, uint32_t &j0, uint32_t lane) {
+    constexpr uint32_t T = kWave * K;
+    uint32_t *const txs = t, *const txe = t + T, *const tys = t + 2 * T, *const tye = t + 3 * T;
+    const uint32_t nx = min(T, n - i0), ny = min(T, m - j0);
+    // all of this wave's reads of the previous tile are done before the
+    // tile is overwritten
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const uint32_t q = lane + k * kWave;
+        if (q < nx) {
+            txs[q] = xs[i0 + q];
+            txe[q] = xe[i0 + q];
+        }
+        if (q < ny) {
+            tys[q] = ys[j0 + q];
+            tye[q] = ye[j0 + q];
+        }
+    }
+    wave_lds_sync();
+    // start state of this lane: merge-path point on diagonal d
+    const uint32_t d = lane * K;
+    uint32_t lo = d > ny ? d - ny : 0, hi = min(d, nx);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (txe[mid] <= tye[d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t i = lo, j = d - lo;   // i > nx only past the end of both lists
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (!found && i < nx && j < ny) {
+            const uint32_t a = txs[i], b = txe[i], c = tys[j], e = tye[j];
+            if (a < e && c < b) found = true;
+            else if (b <= e) i++;
+            else j++;
+        }
+    }
+    if (__any(found)) return true;
+    i0 += uniform(__shfl(i, kWave - 1));
+    j0 += uniform(__shfl(j, kWave - 1));
+    return false;
+}
+
 // Any overlap between X = [xs, xe)[0..n) and Y = [ys, ye)[0..m)?  Result is
-// the one Alg. 2's IntervalJoin returns.  lx, ly: this wave's LDS tiles of
-// 64*K entries each.
+// the one Alg. 2's IntervalJoin returns.
 template <int K>
 __device__ __forceinline__ bool wave_join(const uint32_t *__restrict__ xs, const uint32_t *__restrict__ xe,
-                          uint32_t n, const uint32_t *__restrict__ ys,
-                          const uint32_t *__restrict__ ye, uint32_t m, uint2 *lx, uint2 *ly,
-                          uint32_t lane) {
-    constexpr uint32_t T = kWave * K;
+                                          uint32_t n, const uint32_t *__restrict__ ys,
+                                          const uint32_t *__restrict__ ye, uint32_t m, uint32_t *t,
+                                          uint32_t lane) {
     uint32_t i0 = 0, j0 = 0;
-    while (i0 < n && j0 < m) {
-        const uint32_t nx = min(T, n - i0), ny = min(T, m - j0);
-        // all of this wave's reads of the previous tile are done before the
-        // tile is overwritten
-        wave_lds_sync();
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            const uint32_t t = lane + k * kWave;
-            if (t < nx) lx[t] = make_uint2(xs[i0 + t], xe[i0 + t]);
-            if (t < ny) ly[t] = make_uint2(ys[j0 + t], ye[j0 + t]);
-        }
-        wave_lds_sync();
-        // start state of this lane: merge-path point on diagonal d
-        const uint32_t d = lane * K;
-        uint32_t lo = d > ny ? d - ny : 0, hi = min(d, nx);
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (lx[mid].y <= ly[d - 1 - mid].y) lo = mid + 1;
-            else hi = mid;
-        }
-        uint32_t i = lo, j = d - lo;   // i > nx only past the end of both lists
-        bool found = false;
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (!found && i < nx && j < ny) {
-                const uint2 x = lx[i], y = ly[j];
-                if (x.x < y.y && y.x < x.y) found = true;
-                else if (x.y <= y.y) i++;
-                else j++;
-            }
-        }
-        if (__any(found)) return true;
-        i0 += uniform(__shfl(i, kWave - 1));
-        j0 += uniform(__shfl(j, kWave - 1));
-    }
+    while (i0 < n && j0 < m)
+        if (merge_tile<K>(xs, xe, n, ys, ye, m, t, i0, j0, lane)) return true;
     return false;
 }
 
@@ -106,10 +134,10 @@ template <int K>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(80))) void k_filter_plain(PlainArgs pa) {
     const FilterArgs &a = pa.f;
     const uint32_t xcds = pa.xcds;
-    __shared__ uint2 lds[kWavesPerBlock][2][kWave * K];
+    __shared__ uint32_t lds[kWavesPerBlock][4 * kWave * K];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t w = uniform(threadIdx.x / kWave);
-    uint2 *lx = lds[w][0], *ly = lds[w][1];
+    uint32_t *const lt = lds[w];
     const uint32_t xcd = blockIdx.x % xcds, bx = blockIdx.x / xcds, nbx = gridDim.x / xcds;
     const uint64_t lo = a.n_pairs * xcd / xcds, hi = a.n_pairs * (xcd + 1) / xcds;
     const uint64_t n_waves = uint64_t(nbx) * kWavesPerBlock;
@@ -127,12 +155,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(80))) void k
             const uint32_t nar = uint32_t(ar1 - ar0), nas = uint32_t(as1 - as0);
             const uint32_t nfr = uint32_t(fr1 - fr0), nfs = uint32_t(fs1 - fs0);
             if (!wave_join<K>(a.Ar.s + ar0, a.Ar.e + ar0, nar, a.As.s + as0, a.As.e + as0, nas,
-                              lx, ly, lane)) {
+                              lt, lane)) {
                 v = APRIL_TN;
             } else if (wave_join<K>(a.Ar.s + ar0, a.Ar.e + ar0, nar, a.Fs.s + fs0, a.Fs.e + fs0,
-                                    nfs, lx, ly, lane) ||
+                                    nfs, lt, lane) ||
                        wave_join<K>(a.Fr.s + fr0, a.Fr.e + fr0, nfr, a.As.s + as0, a.As.e + as0,
-                                    nas, lx, ly, lane)) {
+                                    nas, lt, lane)) {
                 v = APRIL_TH;
             } else {
                 v = APRIL_INDECISIVE;
@@ -273,12 +301,14 @@ extern "C" int april_alg2_bytes(const april_lists_t *R, const april_lists_t *S, 
                                 void *hip_stream) {
     clear_error();
     if (int rc = check_lists(R, S)) return rc;
-    if (R->codec != APRIL_CODEC_RAW || S->codec != APRIL_CODEC_RAW)
-        return fail(APRIL_E_INVALID, "byte accounting needs raw lists");
+    if (R->codec != S->codec) return fail(APRIL_E_INVALID, "R and S lists use different codecs");
     if (n_pairs == 0) return APRIL_OK;
     if (!d_r || !d_s || !d_bytes) return fail(APRIL_E_INVALID, "NULL pair/bytes array");
     DeviceState *st;
     if (int rc = device_state(&st)) return rc;
+    if (R->codec == APRIL_CODEC_VBYTE)
+        return launch_alg2_vbyte_bytes(R, S, d_r, d_s, n_pairs, reinterpret_cast<unsigned long long *>(d_bytes),
+                                       st->cus, static_cast<hipStream_t>(hip_stream));
     FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, nullptr, nullptr);
     const uint64_t blocks = std::min<uint64_t>((n_pairs + 255) / 256, uint64_t(st->cus) * 16);
     k_alg2_bytes<<<dim3(uint32_t(blocks)), dim3(256), 0, static_cast<hipStream_t>(hip_stream)>>>(
@@ -339,17 +369,7 @@ extern "C" int april_filter_pairs(const april_lists_t *R, const april_lists_t *S
     }
     FilterArgs a = make_args(R, S, d_r, d_s, n_pairs, d_verdict, counts);
     if (o.schedule == APRIL_SCHED_BATCHED) {
-        // default tile: 256 intervals when a typical A-list fits it (more
-        // waves per CU), else 512 (fewer pieces, and the probe join for
-        // short objects spread over a wide key range).  Measured: 6% faster
-        // at 256 on the at-scale join (mean 177 intervals); 11% faster at
-        // 512 on the skewed one (mean 990; 75.7 against 84.9 ms).
-        if (!o.tile) o.tile = R->n_a + S->n_a <= 256 * (R->n + S->n) ? 256 : 512;
-        // the workgroup bin needs two objects of at least max(tile, wg_min)
-        // intervals: without such objects on both sides, no binning pass
-        if (!o.wg_min) o.wg_min = kDefaultWgMin;
-        const uint64_t need_len = std::max(o.tile, o.wg_min);
-        if (R->max_len < need_len || S->max_len < need_len) o.wg_min = 0xffffffffu;
+        batched_defaults(o, BatchedShape{R->n_a + S->n_a, R->n + S->n, R->max_len, S->max_len});
         const uint64_t need = batched_workspace_bytes(n_pairs);
         if (o.d_workspace) {
             if (o.workspace_bytes < need) return fail(APRIL_E_INVALID, "workspace too small");

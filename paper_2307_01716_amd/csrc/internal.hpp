@@ -161,6 +161,10 @@ uint64_t vbyte_cache_offset();
 int launch_filter_vbyte(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r, const uint32_t *d_s,
                         uint64_t n_pairs, uint8_t *d_verdict, unsigned long long *counts,
                         const april_filter_opts_t &o, int cus, void *workspace, hipStream_t stream);
+// Alg. 2's bytes per pair on compressed lists (april_alg2_bytes).
+int launch_alg2_vbyte_bytes(const april_lists_t *R, const april_lists_t *S, const uint32_t *d_r,
+                            const uint32_t *d_s, uint64_t n_pairs, unsigned long long *d_bytes, int cus,
+                            hipStream_t stream);
 // Candidate pairs (batch query index, S id) of a batch of queries against
 // the uniform MBR grid of S; *count receives the number found (pairs beyond
 // `cap` are not written).

@@ -31,8 +31,11 @@ from collections import OrderedDict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 # sources that define each kernel's code and its launch defaults
-KERNEL_SOURCES = {"k_batched": ["csrc/batched.hip", "csrc/device.hpp", "csrc/filter.hip"],
-                  "k_filter_plain": ["csrc/filter.hip", "csrc/device.hpp"]}
+# (the batched schedule's defaults live in batched.hip, so a change to the
+# plain kernel in filter.hip leaves the batched records valid)
+KERNEL_SOURCES = {"k_batched": ["csrc/batched.hip", "csrc/device.hpp"],
+                  "k_filter_plain": ["csrc/filter.hip", "csrc/device.hpp"],
+                  "k_filter_vbyte": ["csrc/compressed.hip", "csrc/vbyte.hpp", "csrc/device.hpp"]}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 

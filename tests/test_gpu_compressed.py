@@ -245,3 +245,48 @@ def test_partitioned_config_size_against_oracle():
         assert np.array_equal(c.cpu().numpy(), np.bincount(want, minlength=3)), codec
         dR.free()
         dS.free()
+
+
+def _varint_prefix_bytes(s, e, k):
+    """Bytes of the first k intervals of a list in the stream format: the
+    values s0 < e0 < s1 < ... as varint(v_t - v_(t-1) - 1), v_(-1) = 2^32 - 1,
+    7 bits per byte."""
+    if k == 0:
+        return 0
+    v = np.empty(2 * k, np.int64)
+    v[0::2], v[1::2] = s[:k], e[:k]
+    d = (v - np.concatenate([[2 ** 32 - 1], v[:-1]]) - 1) % (2 ** 32)
+    return int(np.maximum(1, -(-np.floor(np.log2(np.maximum(d, 1)) + 1).astype(np.int64) // 7)).sum())
+
+
+def test_alg2_bytes_on_compressed_lists():
+    """april_alg2_bytes on compressed lists: for every pair of the tiny
+    workload, 8 + 16 per list Alg. 2 opens + the stream bytes of each list's
+    prefix that Alg. 2 reads (read counts from the oracle's IntervalJoin,
+    sizes from the stream format) + 1."""
+    R, S, g = synth.configs.tiny()
+    LR, LS = oracle.build_lists(g, R), oracle.build_lists(g, S)
+    r, s = oracle.mbr_join(R, S)
+    want = np.empty(len(r), np.uint64)
+    for p in range(len(r)):
+        ar, as_, fr, fs = LR.A(int(r[p])), LS.A(int(s[p])), LR.F(int(r[p])), LS.F(int(s[p]))
+        hit, k_ar, k_as = oracle.interval_join(ar, as_)
+        k_fr = k_fs = 0
+        lists = 2
+        if hit:
+            lists += 1
+            af, k, k_fs = oracle.interval_join(ar, fs)
+            k_ar = max(k_ar, k)
+            if not af:
+                lists += 1
+                _, k_fr, k = oracle.interval_join(fr, as_)
+                k_as = max(k_as, k)
+        want[p] = (8 + 16 * lists + 1 + _varint_prefix_bytes(*ar, k_ar) + _varint_prefix_bytes(*as_, k_as)
+                   + _varint_prefix_bytes(*fr, k_fr) + _varint_prefix_bytes(*fs, k_fs))
+    dR = upload(g, LR, april.CODEC_VBYTE)
+    dS = upload(g, LS, april.CODEC_VBYTE)
+    by = torch.zeros(len(r), dtype=torch.int64, device="cuda")
+    say(f"[compressed] Alg. 2 bytes over {len(r)} pairs")
+    april.april_alg2_bytes(dR, dS, cuda(r), cuda(s), by)
+    torch.cuda.synchronize()
+    assert np.array_equal(by.cpu().numpy().astype(np.uint64), want)

@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--serve-objects", type=int, default=1_000_000)
     ap.add_argument("--gpu-build-cells", type=int, default=0,
                     help="served queries spanning this many grid cells or more are built on the GPU "
-                         "(0: library default 2^20; 4294967295: never)")
+                         "(0: library default 2^18; 4294967295: never)")
     ap.add_argument("--partitioned", action="store_true",
                     help="partitioned join, raw and compressed lists (own JSON line)")
     ap.add_argument("--part-objects", type=int, default=500_000)
@@ -398,7 +398,7 @@ def serve_bench(args):
            "config": {"workload": f"served: S = {len(S)} star polygons device-resident, grid 2^16; "
                                   "queries 10..10^4 vertices, radius 5e-4..0.05 (log-uniform)",
                       "slots": st["slots"], "cap_pairs": st["cap_pairs"],
-                      "gpu_build_cells": args.gpu_build_cells or (1 << 20)},
+                      "gpu_build_cells": args.gpu_build_cells or (1 << 18)},
            "served": {"saturation_qps": sat_qps, "saturation_pairs_per_s": sat_pairs / t_sat,
                       "levels": levels}}
     print(json.dumps(out), flush=True)
@@ -438,7 +438,7 @@ def partitioned_bench(args):
     ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
     forms, ref = {}, None
     for codec, name, grid in ((april.CODEC_RAW, "raw", {"tile": (256, 512), "chunk": (1, 2)}),
-                              (april.CODEC_VBYTE, "vbyte", {"tile": (256, 512),
+                              (april.CODEC_VBYTE, "vbyte", {"tile": (256, 512, 1024),
                                                             "search_min": (64, 1024)})):
         dR = april.april_lists_to_device(hR, codec=codec, stream=stream)
         dS = april.april_lists_to_device(hS, codec=codec, stream=stream)

@@ -236,7 +236,8 @@ typedef struct {
                               128, 256 or 512 (0 = 256 when the two collections' A-lists
                               average at most 256 intervals, else 512; compressed lists:
                               256, 512, 1024, 0 = 512) */
-    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2);
+    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2,
+                              or 4 with 512-interval tiles);
                               compressed lists: decoding windows (up to 130 intervals each) in
                               the first tile of each join, 1 to 4, capped at the tile (0 = 1) */
     uint32_t thread_max;   /* batched: pairs whose four lists all have at most this many
@@ -301,8 +302,11 @@ int april_filter_workspace_size(uint64_t n_pairs, const april_filter_opts_t *opt
  *   d_r, d_s    device uint32[n_pairs]: pair p is (R object d_r[p], S object d_s[p])
  *   d_verdict   device uint8[n_pairs]: APRIL_TN / APRIL_TH / APRIL_INDECISIVE,
  *               APRIL_BAD_PAIR for an out-of-range index
- *   d_counts    device uint64[3] (TN, TH, INDECISIVE totals) or NULL;
- *               overwritten, not accumulated
+ *   d_counts    uint64[3] (TN, TH, INDECISIVE totals) or NULL; overwritten,
+ *               not accumulated, by three plain stores of the call's last
+ *               kernel, so it may be device memory or pinned host memory
+ *               (hipHostMalloc) that the host reads once the stream passes
+ *               the call
  *   opts        NULL = plain schedule, library defaults
  * Asynchronous on hip_stream; inputs are borrowed until the stream passes
  * the call.  Every verdict is a pure function of the pair's four lists, so
@@ -390,8 +394,9 @@ typedef struct {
     uint32_t host_threads;  /* query-list builder threads (0 = host cores - 2) */
     uint32_t gpu_build_cells;   /* a query whose edges span about this many grid cells
                                    or more has its lists built on the GPU
-                                   (april_build_lists_gpu), the others on the host
-                                   (0 = 2^20, 0xFFFFFFFF = never) */
+                                   (april_build_lists_gpu; one thread builds all such
+                                   queries waiting at once in one call), the others on
+                                   the host (0 = 2^18, 0xFFFFFFFF = never) */
     uint32_t reserved;      /* must be 0 */
     april_filter_opts_t filter;   /* batched-filter tuning (schedule/workspace ignored) */
 } april_serve_opts_t;

@@ -192,6 +192,18 @@ def _dptr(t):
     return t.data_ptr()
 
 
+def _counts_ptr(t):
+    """Address of a counts array: a device tensor, or a pinned host tensor
+    (which the filter's last kernel writes through its device mapping)."""
+    if t is not None and not isinstance(t, int) and not t.is_cuda:
+        if not t.is_pinned():
+            raise ValueError("counts must be a device tensor or a pinned host tensor")
+        if not t.is_contiguous():
+            raise ValueError("counts must be contiguous")
+        return t.data_ptr()
+    return _dptr(t)
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -319,12 +331,13 @@ def april_lists_download(dev: Lists, stream=None) -> Lists:
 def april_filter_pairs(R: Lists, S: Lists, r, s, verdict, counts=None, schedule=SCHED_PLAIN,
                        flags=0, waves=0, stream=None, **tuning) -> int:
     """r, s: int32/uint32 device tensors [P]; verdict: uint8 device tensor [P];
-    counts: int64 device tensor [3] or None.  `tuning` keys: tile, chunk,
+    counts: int64 tensor [3] on the device or in pinned host memory, or
+    None.  `tuning` keys: tile, chunk,
     thread_max, search_min, workspace (a device tensor)."""
     n = int(r.numel()) if hasattr(r, "numel") else (0 if isinstance(r, int) else int(len(r)))
     opts = _opts(schedule, flags, waves, **tuning)
     return _check(lib().april_filter_pairs(R.handle, S.handle, _dptr(r), _dptr(s), n,
-                                           _dptr(verdict), _dptr(counts), C.byref(opts),
+                                           _dptr(verdict), _counts_ptr(counts), C.byref(opts),
                                            _stream(stream)))
 
 
@@ -335,7 +348,7 @@ def april_filter_pairs_static(R: Lists, S: Lists, r, s, verdict, counts=None, sc
     n = int(r.numel()) if hasattr(r, "numel") else (0 if isinstance(r, int) else int(len(r)))
     opts = _opts(schedule, flags, waves, **tuning)
     return _check(lib().april_filter_pairs_static(R.handle, S.handle, _dptr(r), _dptr(s), n,
-                                                  _dptr(verdict), _dptr(counts), C.byref(opts),
+                                                  _dptr(verdict), _counts_ptr(counts), C.byref(opts),
                                                   _stream(stream)))
 
 

@@ -32,7 +32,7 @@ NO_WG = 0xFFFFFFFF
 
 # stage 1 together, then one knob at a time; 0 = the library's default
 STAGES = [
-    {"tile": (128, 256, 512), "chunk": (1, 2), "waves_per_simd": (0, 4, 6)},
+    {"tile": (128, 256, 512), "chunk": (1, 2, 4), "waves_per_simd": (0, 4, 6)},
     {"thread_max": (0, 4, 16)},
     {"wg_min": (0, 1, NO_WG)},   # default 4 tiles; every pair that fits no tile; none
     {"search_min": (0, 4096)},

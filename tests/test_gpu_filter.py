@@ -203,6 +203,30 @@ def test_tiny_from_list_files(tiny, tmp_path):
             assert np.array_equal(cnt, np.bincount(v, minlength=3))
 
 
+def test_tiny_counts_in_pinned_host_memory(tiny):
+    """The totals may go to pinned host memory: after the stream is
+    synchronized it holds the bincount of the oracle's verdicts, for every
+    schedule and codec, and zeros for an empty call."""
+    R, S, g, LR, LS, r, s, v, b = tiny
+    dR, dS = device_lists(g, LR), device_lists(g, LS)
+    vR = april.april_lists_to_device(april.april_lists_download(dR), april.CODEC_VBYTE)
+    vS = april.april_lists_to_device(april.april_lists_download(dS), april.CODEC_VBYTE)
+    for lists, sched, codec in (((dR, dS), "plain", "raw"), ((dR, dS), "batched", "raw"),
+                                ((vR, vS), "batched", "vbyte")):
+        say(f"[tiny] counts to pinned host memory, {sched}, {codec}")
+        host = torch.full((3,), -1, dtype=torch.int64).pin_memory()
+        verdict = torch.empty(len(r), dtype=torch.uint8, device="cuda")
+        april.april_filter_pairs(*lists, cuda(r), cuda(s), verdict, host, **SCHEDULES[sched])
+        torch.cuda.synchronize()
+        assert np.array_equal(host.numpy(), np.bincount(v, minlength=3))
+        assert np.array_equal(verdict.cpu().numpy(), v)
+    host = torch.full((3,), -1, dtype=torch.int64).pin_memory()
+    empty = torch.empty(0, dtype=torch.int32, device="cuda")
+    april.april_filter_pairs(dR, dS, empty, empty, torch.empty(0, dtype=torch.uint8, device="cuda"), host)
+    torch.cuda.synchronize()
+    assert host.tolist() == [0, 0, 0]
+
+
 def test_tiny_waves_and_duplicates(tiny):
     R, S, g, LR, LS, r, s, v, b = tiny
     dR, dS = device_lists(g, LR), device_lists(g, LS)

@@ -437,7 +437,7 @@ def partitioned_bench(args):
     counts = torch.zeros(3, dtype=torch.int64, device="cuda")
     ws = torch.empty(april.april_filter_workspace_size(P), dtype=torch.uint8, device="cuda")
     forms, ref = {}, None
-    for codec, name, grid in ((april.CODEC_RAW, "raw", {"tile": (256, 512), "chunk": (1, 2)}),
+    for codec, name, grid in ((april.CODEC_RAW, "raw", {"tile": (256, 512), "chunk": (1, 2, 4)}),
                               (april.CODEC_VBYTE, "vbyte", {"tile": (256, 512, 1024),
                                                             "search_min": (64, 1024)})):
         dR = april.april_lists_to_device(hR, codec=codec, stream=stream)

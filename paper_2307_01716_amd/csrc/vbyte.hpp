@@ -19,7 +19,9 @@
 
 namespace april {
 
-// Wave-uniform decoder state of one list.
+typedef const __attribute__((address_space(1))) uint32_t *GWords;   // global memory
+
+// Decoder state of one list (wave-uniform, but for the prefetched words).
 struct VCursor {
     const uint8_t *base;   // the list's stream
     uint32_t nbytes;       // stream length
@@ -27,6 +29,14 @@ struct VCursor {
     uint32_t pos;          // first byte of the next value
     uint32_t prev;         // last absolute value decoded
     uint32_t g;            // values decoded so far
+    // The aligned 256 bytes that follow the window being decoded, loaded
+    // while it is decoded: lane l holds word l of the block at byte pfo of
+    // the stream, lane 63 also words 64 and 65.  The next window starts at
+    // pfo or pfo + 4, so its words are these.  Window starts are aligned
+    // addresses, all congruent mod 4 as stream offsets: a pfo of another
+    // residue marks that nothing is loaded.
+    uint32_t pfo;
+    uint32_t pw, px0, px1;
 };
 
 // Cross-lane steps on DPP (VALU operand routing, no trip through the LDS
@@ -65,6 +75,8 @@ __device__ __forceinline__ VCursor vcursor(const uint8_t *bytes, uint64_t b0, ui
     c.pos = 0;
     c.prev = 0xffffffffu;
     c.g = 0;
+    c.pfo = 1u - uint32_t(reinterpret_cast<uintptr_t>(c.base) & 3u);   // no window starts there
+    c.pw = c.px0 = c.px1 = 0u;
     return c;
 }
 
@@ -129,6 +141,12 @@ __host__ __device__ __forceinline__ LaneVals vdecode_lane(uint32_t w, uint32_t w
 // With `write_pending` the pending start carried in from the previous window
 // is written to bs[0] (needed when bs is reused; not when the caller
 // advances bs by k between windows).  bs/be must hold 130 entries.
+//
+// Unless the stream ends within the window, the last value that starts in
+// its 256 bytes ends at window byte 256 to 260, so the next window begins at
+// byte 256 or 260 of this one: the call loads those bytes for the next call
+// before it decodes, and the next call finds its words already in registers
+// (the loads stay within the 512 bytes that follow a stream's end).
 __device__ __forceinline__ uint32_t vdecode_window(VCursor &c, uint32_t *bs, uint32_t *be, bool write_pending,
                                                    uint32_t lane) {
     if (c.g >= c.nvals) return 0;
@@ -136,13 +154,41 @@ __device__ __forceinline__ uint32_t vdecode_window(VCursor &c, uint32_t *bs, uin
     const uintptr_t a = reinterpret_cast<uintptr_t>(p) & ~uintptr_t(3);
     const uint32_t skip = uint32_t(reinterpret_cast<uintptr_t>(p) - a);     // bytes before the value start
     const uint32_t *wp = reinterpret_cast<const uint32_t *>(a);
-    const uint32_t w = wp[lane];
-    uint32_t wn = from_lane_above(w);
-    if (lane == 63) wn = wp[64];
-    const uint32_t wprev = from_lane_below(w);
+    const GWords gw = (GWords)wp;
+    const uint32_t wofs = c.pos - skip;   // the window's stream offset
+    uint32_t w, wn;
+    if (wofs == c.pfo) {
+        w = c.pw;
+        wn = from_lane_above(w);
+        if (lane == 63) wn = c.px0;
+    } else if (wofs == c.pfo + 4u) {
+        w = from_lane_above(c.pw);
+        if (lane == 63) w = c.px0;
+        wn = from_lane_above(w);
+        if (lane == 63) wn = c.px1;
+    } else {
+        w = gw[lane];
+        wn = from_lane_above(w);
+        if (lane == 63) wn = gw[64];
+    }
     // a window spans 256 bytes (+4 seen by lane 63)
     const uint32_t avail = c.nbytes - c.pos;
+    const uint32_t wprev = from_lane_below(w);
     const LaneVals L = vdecode_lane(w, wn, wprev, lane, skip, skip + (avail < 512u ? avail : 512u));
+    // issued once w and wn are in registers (the empty asm takes them, and
+    // no memory access moves across it), so that no wait for them waits
+    // for these loads too
+    asm volatile("" ::"v"(w), "v"(wn) : "memory");
+    if (avail > 260u) {
+        c.pfo = wofs + 256u;
+        c.pw = gw[64 + lane];
+        if (lane == 63) {
+            c.px0 = gw[128];
+            c.px1 = gw[129];
+        }
+    } else {
+        c.pfo = wofs + 1u;
+    }
     const uint32_t inc_vals = wave_incl_scan(L.nval), inc_sum = wave_incl_scan(L.local);
     const uint32_t before_vals = inc_vals - L.nval, before_sum = inc_sum - L.local;
     const uint32_t V = __builtin_amdgcn_readlane(inc_vals, 63);

@@ -298,6 +298,8 @@ def skewed_leg(args, stream):
         out["batched"]["hbm_frac"] = out["batched"]["hbm_GBps"] / HBM_PEAK_GBS
     else:
         out["batched"]["traffic_bytes"] = None
+    out["batched"]["valu"] = profiling.read_valu(os.path.join(HERE, "profiles", f"{kname}_skewed_valu.txt"),
+                                                 kname, cfg, P, ms_b)
     if not args.skewed_no_plain:
         ts = []
         for k in range(2):
@@ -414,7 +416,7 @@ def partitioned_bench(args):
     import torch
 
     import synth
-    from paper_2307_01716_amd import april, partitioned, tune
+    from paper_2307_01716_amd import april, partitioned, profiling, tune
 
     assert torch.cuda.is_available(), "no HIP device"
     t0 = time.time()
@@ -470,6 +472,15 @@ def partitioned_bench(args):
         forms[name]["alg_GBps"] = forms[name]["alg_bytes"] / (ms / 1e3) / 1e9
         forms[name]["alg_frac"] = forms[name]["alg_GBps"] / HBM_PEAK_GBS
         del by
+        # measured HBM traffic and VALU issue, from the committed rocprofv3
+        # records when they were taken on these sources and this launch
+        kname = "k_batched" if codec == april.CODEC_RAW else "k_filter_vbyte"
+        stem = os.path.join(HERE, "profiles", f"{kname}_partitioned500k")
+        tr = profiling.read_traffic(stem + "_traffic.txt", kname, cfg, P)
+        forms[name]["traffic_bytes"] = tr
+        if tr is not None:
+            forms[name]["hbm_frac"] = tr / (ms / 1e3) / 1e9 / HBM_PEAK_GBS
+        forms[name]["valu"] = profiling.read_valu(stem + "_valu.txt", kname, cfg, P, ms)
         log(f"{name}: {ms:.3f} ms, {P / ms / 1e6:.3f} G pairs/s, lists {nbytes / 1e9:.2f} GB on device")
         del dR, dS
         torch.cuda.synchronize()
@@ -484,7 +495,8 @@ def partitioned_bench(args):
            "forms": forms,
            "compression": forms["raw"]["device_bytes"] / forms["vbyte"]["device_bytes"],
            "roofline": {"bound": "hbm", "achieved": forms["vbyte"]["alg_GBps"], "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": forms["vbyte"]["alg_frac"], "traffic": None}}
+                        "unit": "GB/s", "frac": forms["vbyte"]["alg_frac"],
+                        "traffic": forms["vbyte"]["traffic_bytes"]}}
     print(json.dumps(out), flush=True)
 
 
@@ -965,6 +977,14 @@ def main():
     if "plain" in forms:
         forms["plain"]["traffic_bytes"] = profiling.read_traffic(
             os.path.join(HERE, "profiles", "k_filter_plain_scale200k_traffic.txt"), "k_filter_plain", {}, P)
+    # VALU issue (the kernels' instruction counts from the same records)
+    if args.workload == "scale":
+        for fname, kn, kc in (("batched", "k_batched", forms.get("batched", {}).get("tuning", {})),
+                              ("plain", "k_filter_plain", {})):
+            if fname in forms:
+                forms[fname]["valu"] = profiling.read_valu(
+                    os.path.join(HERE, "profiles", f"{kn}_scale200k_valu.txt"), kn, kc, P,
+                    forms[fname]["kernel_ms"])
     out = {
         "metric": "candidate pairs filtered/s (" + (
             "batched persistent schedule, hipGraph replay" if main_form == "batched"

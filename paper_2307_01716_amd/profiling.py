@@ -5,6 +5,8 @@ Reads the CSV files that `rocprofv3 --kernel-trace --stats` and
 
 * kernel statistics (calls, average / min / max duration per kernel);
 * per-dispatch counters of the filter kernels;
+* VALU instructions per launch (SQ_INSTS_VALU), against the device's peak
+  issue rate, keyed like the traffic records;
 * HBM traffic per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
   each scaled by what the same counter reads for a device-to-device copy of
   known size (the copies `bench.py --copy-calibration` makes before its
@@ -17,6 +19,8 @@ Command line:
     python -m paper_2307_01716_amd.profiling traffic --fetch DIR --write DIR \
         --kernel k_batched --config tile=512,chunk=2 --pairs N --alg-bytes B \
         --command "..." --out FILE
+    python -m paper_2307_01716_amd.profiling valu --pmc DIR --kernel k_batched \
+        --pairs N --command "..." --out FILE
 """
 
 from __future__ import annotations
@@ -37,6 +41,10 @@ KERNEL_SOURCES = {"k_batched": ["csrc/batched.hip", "csrc/device.hpp"],
                   "k_filter_plain": ["csrc/filter.hip", "csrc/device.hpp"],
                   "k_filter_vbyte": ["csrc/compressed.hip", "csrc/vbyte.hpp", "csrc/device.hpp"]}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
+# Peak VALU issue rate of the device: 256 CUs x 4 SIMDs, each issuing one
+# wave64 VALU instruction every 4 cycles (16 lanes wide) at 2.4 GHz, i.e.
+# 39.3 T 32-bit lane operations per second.
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def source_digest(kernel: str) -> str:
@@ -147,9 +155,24 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int = 1 << 
     return out
 
 
-def read_traffic(path: str, kernel: str, config: dict, pairs: int):
-    """Traffic bytes per launch recorded in `path`, if that record was taken
-    on the current sources of `kernel`, with `config` and `pairs`; else None."""
+def valu(pmc_dir: str, kernel: str, parts=None):
+    """VALU instructions (SQ_INSTS_VALU, wave64 instructions) per launch of
+    `kernel` (with `parts`: the sum of their per-dispatch averages)."""
+    total, n, per_part = 0.0, None, {}
+    for part in parts or [kernel]:
+        x = _per_kernel(pmc_dir, "SQ_INSTS_VALU", part)
+        per_part[part] = sum(x) / len(x)
+        total += sum(x) / len(x)
+        n = len(x) if n is None else min(n, len(x))
+    out = {"insts_per_launch": total, "dispatches": n}
+    if parts:
+        out["parts"] = per_part
+    return out
+
+
+def _record(path: str, kernel: str, config: dict, pairs: int):
+    """The record in `path`, if it was taken on the current sources of
+    `kernel`, with `config` and `pairs`; else None."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -158,7 +181,27 @@ def read_traffic(path: str, kernel: str, config: dict, pairs: int):
         return None
     if rec.get("config") != config or rec.get("pairs") != pairs:
         return None
-    return rec["traffic"]["traffic_bytes"]
+    return rec
+
+
+def read_traffic(path: str, kernel: str, config: dict, pairs: int):
+    """Traffic bytes per launch recorded in `path`, if that record was taken
+    on the current sources of `kernel`, with `config` and `pairs`; else None."""
+    rec = _record(path, kernel, config, pairs)
+    return rec["traffic"]["traffic_bytes"] if rec else None
+
+
+def read_valu(path: str, kernel: str, config: dict, pairs: int, kernel_ms: float):
+    """VALU issue of a launch taking `kernel_ms`, from the instruction count
+    recorded in `path` (same conditions as read_traffic), against the
+    device's peak issue rate; None without a valid record."""
+    rec = _record(path, kernel, config, pairs)
+    if not rec:
+        return None
+    insts = rec["valu"]["insts_per_launch"]
+    rate = insts / (kernel_ms / 1e3)
+    return {"insts_per_launch": insts, "insts_per_pair": insts / pairs, "issue_rate": rate,
+            "peak": VALU_ISSUE_PEAK, "unit": "wave64 VALU instructions/s", "frac": rate / VALU_ISSUE_PEAK}
 
 
 def main():
@@ -166,6 +209,14 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("stats")
     a.add_argument("trace_dir")
+    v = sub.add_parser("valu")
+    v.add_argument("--pmc", required=True, help="a --pmc SQ_INSTS_VALU output folder")
+    v.add_argument("--kernel", default="k_batched")
+    v.add_argument("--parts", default="")
+    v.add_argument("--config", default="")
+    v.add_argument("--pairs", type=int, required=True)
+    v.add_argument("--command", default="")
+    v.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -191,6 +242,15 @@ def main():
                 if n.startswith(args.kernel) or n == COPY_KERNEL:
                     print(f"{os.path.basename(d.rstrip('/'))} dispatch {disp} {n}: " +
                           " ".join(f"{k}={x:.6g}" for k, x in sorted(v.items())))
+    elif args.cmd == "valu":
+        cfg = {k: int(x) for k, x in (kv.split("=") for kv in args.config.split(","))} if args.config else {}
+        va = valu(args.pmc, args.kernel, parts=[p for p in args.parts.split(",") if p] or None)
+        rec = {"kernel": args.kernel, "config": cfg, "pairs": args.pairs,
+               "source_sha256": source_digest(args.kernel), "valu": va, "command": args.command}
+        with open(args.out, "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+            f.write("\n")
+        print(json.dumps(rec, indent=1, sort_keys=True))
     else:
         cfg = {k: int(v) for k, v in (kv.split("=") for kv in args.config.split(","))} if args.config else {}
         tr = traffic(args.fetch, args.write, args.kernel,

@@ -5,7 +5,10 @@
 * a traffic record counts only while it was taken on the kernel's current
   sources, with the same launch configuration and workload size;
 * the copy calibration scales FETCH_SIZE / WRITE_SIZE by what a copy of known
-  size reads for them.
+  size reads for them;
+* VALU records sum the instruction counts of a launch's kernels, and their
+  issue fraction is instructions per second over 256 x 4 SIMDs issuing one
+  wave64 instruction per 4 cycles at 2.4 GHz.
 """
 
 import csv
@@ -69,3 +72,20 @@ def test_committed_records_name_their_command():
             rec = json.load(f)
         assert "rocprofv3 --pmc FETCH_SIZE" in rec["command"] and "rocprofv3 --pmc WRITE_SIZE" in rec["command"]
         assert rec["traffic"]["traffic_bytes"] > 0
+
+
+def test_valu_record_and_issue_fraction(tmp_path):
+    k1 = "void april::(anonymous namespace)::k_bin(april::(anonymous namespace)::BatchArgs, unsigned int)"
+    k2 = "void april::(anonymous namespace)::k_batched<512, 4>(april::(anonymous namespace)::BatchArgs)"
+    _write_counters(tmp_path, "sq", [(1, k1, "SQ_INSTS_VALU", 100.0), (2, k2, "SQ_INSTS_VALU", 1000.0),
+                                     (3, k1, "SQ_INSTS_VALU", 300.0), (4, k2, "SQ_INSTS_VALU", 3000.0)])
+    v = profiling.valu(str(tmp_path / "sq"), "k_batched", parts=["k_bin", "k_batched"])
+    assert v["insts_per_launch"] == 200.0 + 2000.0 and v["dispatches"] == 2
+    assert profiling.VALU_ISSUE_PEAK == 614.4e9
+    rec = {"kernel": "k_batched", "config": {}, "pairs": 10, "command": "",
+           "source_sha256": profiling.source_digest("k_batched"), "valu": {"insts_per_launch": 614.4e6}}
+    p = tmp_path / "v.txt"
+    p.write_text(json.dumps(rec))
+    got = profiling.read_valu(str(p), "k_batched", {}, 10, kernel_ms=2.0)   # 614.4e6 in 2 ms
+    assert abs(got["frac"] - 0.5) < 1e-12 and got["insts_per_pair"] == 61.44e6
+    assert profiling.read_valu(str(p), "k_batched", {}, 11, kernel_ms=2.0) is None

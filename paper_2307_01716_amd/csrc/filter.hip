@@ -46,11 +46,12 @@ namespace {
 // of 64*K words at t, t + 64K, t + 128K, t + 192K (X starts, X ends, Y starts,
 // Y ends).  A lane's merge-path search reads ends only, so these reads fall
 // on consecutive words rather than every other word of interleaved
-// (start, end) pairs: LDS bank conflicts per LDS instruction fell from 2.5
-// to about 0.9 at scale, and the kernel from 6.07 to 5.83 ms.  (Padding one word
-// per 64, against the remaining two-way conflicts of lanes two elements
-// apart, and a first tile of 64 intervals, against loads past an early
-// overlap, each made it slower: 6.32 and 6.49 ms.)
+// (start, end) pairs: LDS bank conflict cycles per LDS instruction fell
+// from 2.5 to 1.5 at scale, and the kernel from 6.09-6.11 to 6.02-6.06 ms.
+// (Padding one word per 64, against the remaining two-way conflicts of lanes
+// two elements apart, and a first tile of 64 intervals, against loads past
+// an early overlap, each made it slower: 6.32 and 6.49 ms against 6.07 ms
+// in the same runs.)
 
 // One tile of the merge: both lists' next 64*K intervals from (i0, j0) are
 // staged in LDS, every lane runs K steps of Alg. 2's loop from its

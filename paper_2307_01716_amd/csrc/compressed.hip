@@ -79,10 +79,23 @@ __device__ __forceinline__ VCursor cursor_at(const ListRef &x) {
     return vcursor(x.L.bytes, x.L.boff[x.obj], x.L.boff[x.obj + 1], x.n);
 }
 
-// Does Y (compressed, streamed) overlap the X tile ts/te (nt > 0 sorted,
-// disjoint intervals in LDS)?  Y is decoded from the last block whose first
-// start is at or before the tile's first start, window by window into ys/ye,
-// until a Y start reaches the tile's end.
+// Pad the X tile's entries nt .. TILE-1 with 0xFFFFFFFF (start and end): a
+// padding end lies above every start, so a search of the tile's ends stops
+// at index nt at most, and a padding start meets no interval.
+template <int TILE>
+__device__ __forceinline__ void pad_tile(uint32_t *ts, uint32_t *te, uint32_t nt, uint32_t lane) {
+    for (uint32_t i = nt + lane; i < TILE; i += 64) {
+        ts[i] = 0xffffffffu;
+        te[i] = 0xffffffffu;
+    }
+}
+
+// Does Y (compressed, streamed) overlap the X tile ts/te (0 < nt < TILE
+// sorted, disjoint intervals in LDS, padded to TILE entries; te = ts +
+// TILE)?  Y is decoded from the last block whose first start is at or
+// before the tile's first start, window by window into ys/ye, until a Y
+// start reaches the tile's end.
+template <int TILE>
 __device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *te, uint32_t nt, const ListRef &Y,
                                            uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
     const uint64_t yb0 = Y.L.boff[Y.obj], yb1 = Y.L.boff[Y.obj + 1];
@@ -107,13 +120,16 @@ __device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *t
         uint32_t s1 = v1 ? ys[lane + 64] : 0u, e1 = v1 ? ye[lane + 64] : 0u;
         if (e0 <= x_lo || s0 >= x_hi) e0 = s0 = 0;
         if (e1 <= x_lo || s1 >= x_hi) e1 = s1 = 0;
-        uint32_t p0 = 0, p1 = 0;
-        for (uint32_t step = 1u << (31 - __builtin_clz(nt)); step; step >>= 1) {
-            const uint32_t q0 = p0 + step, q1 = p1 + step;
-            if (q0 <= nt && te[q0 - 1] <= s0) p0 = q0;
-            if (q1 <= nt && te[q1 - 1] <= s1) p1 = q1;
+        // the first tile end above each start: log2(TILE) fixed rounds over
+        // the padded tile, no bounds tests (the raw batched kernel's search)
+        const uint32_t *p0 = te, *p1 = te;
+#pragma unroll
+        for (uint32_t S = TILE / 2; S > 0; S >>= 1) {
+            const uint32_t u0 = p0[S - 1], u1 = p1[S - 1];
+            p0 = u0 <= s0 ? p0 + S : p0;
+            p1 = u1 <= s1 ? p1 + S : p1;
         }
-        const bool hit = (p0 < nt && ts[p0] < e0) || (p1 < nt && ts[p1] < e1);
+        const bool hit = (p0[-TILE] < e0) || (p1[-TILE] < e1);   // the matching starts
         if (__any(hit)) return true;
         // every later Y interval starts after this tile ends
         if (k == 0 || ys[k - 1] >= x_hi) break;
@@ -138,11 +154,15 @@ __device__ bool cjoin(const ListRef &X, const ListRef &Y, uint32_t *ts, uint32_t
             nt += vdecode_window(cx, ts + nt, te + nt, false, lane);
         }
         wave_lds_sync();
-        if (nt && probe_tile(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
+        // a start decoded after the tile's last full interval opens the next
+        // tile (taken before the padding covers it)
+        const uint32_t pend = (cx.g & 1u) ? ts[nt] : 0u;
+        wave_lds_sync();
+        pad_tile<TILE>(ts, te, nt, lane);
+        wave_lds_sync();
+        if (nt && probe_tile<TILE>(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
         cap = TILE;
-        // a start decoded after the tile's last full interval opens the next tile
         if (cx.g & 1u) {
-            const uint32_t pend = ts[nt];
             wave_lds_sync();
             if (lane == 0) ts[0] = pend;
         }
@@ -162,19 +182,20 @@ __device__ bool rjoin(const uint32_t *xs, const uint32_t *xe, uint32_t nx, uint3
                       const ListRef &Y, uint32_t *ts, uint32_t *te, uint32_t *ys, uint32_t *ye,
                       uint32_t search_min, uint32_t lane) {
     if (nx == 0 || Y.n == 0) return false;
-    for (uint32_t t0 = 0; t0 < nx; t0 += TILE) {
-        const uint32_t nt = min(uint32_t(TILE), nx - t0);
+    // tiles of TILE - 1 intervals, so that every tile has a padding entry
+    for (uint32_t t0 = 0; t0 < nx; t0 += TILE - 1) {
+        const uint32_t nt = min(uint32_t(TILE - 1), nx - t0);
         const uint32_t key = (t0 << 1) | list;
         if (*held != key) {
             wave_lds_sync();
-            for (uint32_t i = lane; i < nt; i += 64) {
-                ts[i] = xs[t0 + i];
-                te[i] = xe[t0 + i];
+            for (uint32_t i = lane; i < TILE; i += 64) {
+                ts[i] = i < nt ? xs[t0 + i] : 0xffffffffu;
+                te[i] = i < nt ? xe[t0 + i] : 0xffffffffu;
             }
             wave_lds_sync();
             *held = key;
         }
-        if (probe_tile(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
+        if (probe_tile<TILE>(ts, te, nt, Y, ys, ye, search_min, lane)) return true;
     }
     return false;
 }

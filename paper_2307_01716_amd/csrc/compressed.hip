@@ -70,13 +70,19 @@ __device__ __forceinline__ uint32_t first_gt(const uint32_t *__restrict__ arr, u
     return mask ? lo + uint32_t(__builtin_ctzll(mask)) : hi;
 }
 
+// A list of one object: its collection's arrays stay in the kernel's
+// argument segment (read with scalar loads where they are used), so that a
+// reference costs two scalar registers, not twelve.
+typedef const __attribute__((address_space(4))) CList KList;
+typedef const __attribute__((address_space(4))) CArgs KArgs;
+
 struct ListRef {
-    CList L;
+    KList *L;
     uint32_t obj, n;
 };
 
 __device__ __forceinline__ VCursor cursor_at(const ListRef &x) {
-    return vcursor(x.L.bytes, x.L.boff[x.obj], x.L.boff[x.obj + 1], x.n);
+    return vcursor(x.L->bytes, x.L->boff[x.obj], x.L->boff[x.obj + 1], x.n);
 }
 
 // Pad the X tile's entries nt .. TILE-1 with 0xFFFFFFFF (start and end): a
@@ -98,15 +104,15 @@ __device__ __forceinline__ void pad_tile(uint32_t *ts, uint32_t *te, uint32_t nt
 template <int TILE>
 __device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *te, uint32_t nt, const ListRef &Y,
                                            uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
-    const uint64_t yb0 = Y.L.boff[Y.obj], yb1 = Y.L.boff[Y.obj + 1];
-    const uint64_t yblk = Y.L.blk[Y.obj];
-    const uint32_t ynblk = uint32_t(Y.L.blk[Y.obj + 1] - yblk);
+    const uint64_t yb0 = Y.L->boff[Y.obj], yb1 = Y.L->boff[Y.obj + 1];
+    const uint64_t yblk = Y.L->blk[Y.obj];
+    const uint32_t ynblk = uint32_t(Y.L->blk[Y.obj + 1] - yblk);
     const uint32_t x_lo = ts[0], x_hi = te[nt - 1];
-    VCursor cy = vcursor(Y.L.bytes, yb0, yb1, Y.n);
+    VCursor cy = vcursor(Y.L->bytes, yb0, yb1, Y.n);
     if (Y.n > search_min && ynblk > 1) {
-        uint32_t b = first_gt(Y.L.bval + yblk, ynblk, x_lo, lane);
+        uint32_t b = first_gt(Y.L->bval + yblk, ynblk, x_lo, lane);
         b = b ? b - 1 : 0;
-        if (b) cy = vcursor_block(Y.L.bytes, yb0, yb1, Y.n, b, Y.L.bval[yblk + b], Y.L.bpos[yblk + b]);
+        if (b) cy = vcursor_block(Y.L->bytes, yb0, yb1, Y.n, b, Y.L->bval[yblk + b], Y.L->bpos[yblk + b]);
     }
     while (cy.g < cy.nvals) {
         wave_lds_sync();
@@ -237,6 +243,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
             const uint32_t cnt = uint32_t(min<uint64_t>(64, hi - g0));
             for (uint32_t i = 0; i < cnt; i++) {
                 const uint64_t p = g0 + i;
+                // the list arrays are read from the argument segment through a
+                // pointer the compiler cannot see through, so they hold no
+                // scalar registers between their uses
+                KArgs *pa = (KArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+                asm volatile("" : "+s"(pa));
                 const uint32_t r = uniform(a.r[p]), s = uniform(a.s[p]);
                 if (r >= a.n_r || s >= a.n_s) {
                     if (lane == 0) a.verdict[p] = APRIL_BAD_PAIR;
@@ -251,13 +262,13 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                     // R from the decode cache (decoded once while consecutive
                     // pairs share it), S streamed
                     if (r != cached) {
-                        decode_all(ListRef{a.Ar, r, nar}, cas, cae, lane);
-                        decode_all(ListRef{a.Fr, r, nfr}, cfs, cfe, lane);
+                        decode_all(ListRef{&pa->Ar, r, nar}, cas, cae, lane);
+                        decode_all(ListRef{&pa->Fr, r, nfr}, cfs, cfe, lane);
                         __threadfence_block();   // the wave's stores, visible to all its lanes
                         cached = r;
                         held = kNoTile;
                     }
-                    const ListRef SA{a.As, s, nas}, SF{a.Fs, s, nfs};
+                    const ListRef SA{&pa->As, s, nas}, SF{&pa->Fs, s, nfs};
                     if (!rjoin<TILE>(cas, cae, nar, 0, &held, SA, ts, te, ys, ye, a.search_min, lane))
                         v = APRIL_TN;
                     else if (rjoin<TILE>(cas, cae, nar, 0, &held, SF, ts, te, ys, ye, a.search_min, lane) ||
@@ -273,10 +284,10 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                     continue;
                 }
                 const bool xs = max(nas, nfs) < max(nar, nfr);
-                const ListRef XA{xs ? a.As : a.Ar, xs ? s : r, xs ? nas : nar};
-                const ListRef XF{xs ? a.Fs : a.Fr, xs ? s : r, xs ? nfs : nfr};
-                const ListRef YA{xs ? a.Ar : a.As, xs ? r : s, xs ? nar : nas};
-                const ListRef YF{xs ? a.Fr : a.Fs, xs ? r : s, xs ? nfr : nfs};
+                const ListRef XA{xs ? &pa->As : &pa->Ar, xs ? s : r, xs ? nas : nar};
+                const ListRef XF{xs ? &pa->Fs : &pa->Fr, xs ? s : r, xs ? nfs : nfr};
+                const ListRef YA{xs ? &pa->Ar : &pa->As, xs ? r : s, xs ? nar : nas};
+                const ListRef YF{xs ? &pa->Fr : &pa->Fs, xs ? r : s, xs ? nfr : nfs};
                 held = kNoTile;   // the decoding joins overwrite ts/te
                 if (!cjoin<TILE>(XA, YA, ts, te, ys, ye, a.search_min, a.first_cap, lane)) v = APRIL_TN;
                 else if (cjoin<TILE>(XA, YF, ts, te, ys, ye, a.search_min, a.first_cap, lane) ||

@@ -96,25 +96,25 @@ __device__ __forceinline__ void pad_tile(uint32_t *ts, uint32_t *te, uint32_t nt
     }
 }
 
-// Does Y (compressed, streamed) overlap the X tile ts/te (0 < nt < TILE
-// sorted, disjoint intervals in LDS, padded to TILE entries; te = ts +
-// TILE)?  Y is decoded from the last block whose first start is at or
-// before the tile's first start, window by window into ys/ye, until a Y
-// start reaches the tile's end.
+// The first entry of the padded tile's ends above `key` (as an address;
+// the matching start lies TILE entries below): log2(TILE) fixed rounds, no
+// bounds tests, as in the raw batched kernel.
 template <int TILE>
-__device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *te, uint32_t nt, const ListRef &Y,
-                                           uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
-    const uint64_t yb0 = Y.L->boff[Y.obj], yb1 = Y.L->boff[Y.obj + 1];
-    const uint64_t yblk = Y.L->blk[Y.obj];
-    const uint32_t ynblk = uint32_t(Y.L->blk[Y.obj + 1] - yblk);
-    const uint32_t x_lo = ts[0], x_hi = te[nt - 1];
-    VCursor cy = vcursor(Y.L->bytes, yb0, yb1, Y.n);
-    if (Y.n > search_min && ynblk > 1) {
-        uint32_t b = first_gt(Y.L->bval + yblk, ynblk, x_lo, lane);
-        b = b ? b - 1 : 0;
-        if (b) cy = vcursor_block(Y.L->bytes, yb0, yb1, Y.n, b, Y.L->bval[yblk + b], Y.L->bpos[yblk + b]);
-    }
-    while (cy.g < cy.nvals) {
+__device__ __forceinline__ const uint32_t *tile_first_above(const uint32_t *te, uint32_t key) {
+    const uint32_t *p = te;
+#pragma unroll
+    for (uint32_t S = TILE / 2; S > 0; S >>= 1) p = p[S - 1] <= key ? p + S : p;
+    return p;
+}
+
+// Decode Y window by window from cursor cy until cy.g reaches `gend` (or the
+// list ends), testing every decoded interval against the tile: 1 = an
+// overlap, 2 = the decoded intervals have passed the tile's end (nothing
+// later can meet it), 0 = neither.
+template <int TILE>
+__device__ __forceinline__ uint32_t scan_windows(VCursor &cy, uint32_t gend, const uint32_t *te, uint32_t x_lo,
+                                                 uint32_t x_hi, uint32_t *ys, uint32_t *ye, uint32_t lane) {
+    while (cy.g < gend) {
         wave_lds_sync();
         const uint32_t k = vdecode_window(cy, ys, ye, true, lane);
         wave_lds_sync();
@@ -126,8 +126,6 @@ __device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *t
         uint32_t s1 = v1 ? ys[lane + 64] : 0u, e1 = v1 ? ye[lane + 64] : 0u;
         if (e0 <= x_lo || s0 >= x_hi) e0 = s0 = 0;
         if (e1 <= x_lo || s1 >= x_hi) e1 = s1 = 0;
-        // the first tile end above each start: log2(TILE) fixed rounds over
-        // the padded tile, no bounds tests (the raw batched kernel's search)
         const uint32_t *p0 = te, *p1 = te;
 #pragma unroll
         for (uint32_t S = TILE / 2; S > 0; S >>= 1) {
@@ -136,9 +134,63 @@ __device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *t
             p1 = u1 <= s1 ? p1 + S : p1;
         }
         const bool hit = (p0[-TILE] < e0) || (p1[-TILE] < e1);   // the matching starts
-        if (__any(hit)) return true;
+        if (__any(hit)) return 1;
         // every later Y interval starts after this tile ends
-        if (k == 0 || ys[k - 1] >= x_hi) break;
+        if (k == 0 || ys[k - 1] >= x_hi) return 2;
+    }
+    return 0;
+}
+
+// Does Y (compressed, streamed) overlap the X tile ts/te (0 < nt < TILE
+// sorted, disjoint intervals in LDS, padded to TILE entries; te = ts +
+// TILE)?  A short Y is decoded from its start.  A longer one is taken block
+// by block (64 intervals, whose starts the block index holds): the blocks
+// from the last one starting at or before the tile's first start to the
+// last one starting below its end are tested against the tile 64 at a time,
+// a lane per block (its intervals lie in [its first start, the next
+// block's first start), and only a tile interval meeting that range can
+// meet one of them), and only the blocks that pass are decoded, window by
+// window from their block-index entry (or onward from where the previous
+// window stopped).
+template <int TILE>
+__device__ __forceinline__ bool probe_tile(const uint32_t *ts, const uint32_t *te, uint32_t nt, const ListRef &Y,
+                                           uint32_t *ys, uint32_t *ye, uint32_t search_min, uint32_t lane) {
+    const uint64_t yb0 = Y.L->boff[Y.obj], yb1 = Y.L->boff[Y.obj + 1];
+    const uint64_t yblk = Y.L->blk[Y.obj];
+    const uint32_t ynblk = uint32_t(Y.L->blk[Y.obj + 1] - yblk);
+    const uint32_t x_lo = ts[0], x_hi = te[nt - 1];
+    VCursor cy = vcursor(Y.L->bytes, yb0, yb1, Y.n);
+    if (Y.n <= search_min || ynblk <= 1) return scan_windows<TILE>(cy, cy.nvals, te, x_lo, x_hi, ys, ye, lane) == 1;
+    const uint32_t *bval = Y.L->bval + yblk, *bpos = Y.L->bpos + yblk;
+    uint32_t b0 = first_gt(bval, ynblk, x_lo, lane);
+    b0 = b0 ? b0 - 1 : 0;
+    const uint32_t b1 = first_gt(bval, ynblk, x_hi - 1, lane);   // the first block starting at or after x_hi
+    bool started = false;
+    for (uint32_t bb = b0; bb < b1; bb += 64) {
+        const uint32_t b = bb + lane;
+        bool need = false;
+        uint32_t bv = 0, bp = 0;
+        if (b < b1) {
+            bv = bval[b];
+            bp = bpos[b];
+            const uint32_t bn = b + 1 < ynblk ? bval[b + 1] : 0xffffffffu;
+            need = tile_first_above<TILE>(te, bv)[-TILE] < bn;
+        }
+        uint64_t mask = __ballot(need);
+        while (mask) {
+            const uint32_t jl = uint32_t(__builtin_ctzll(mask));
+            mask &= mask - 1;
+            const uint32_t blk = bb + jl;
+            const uint32_t gend = min(cy.nvals, 2 * 64 * (blk + 1));   // values through the block's last end
+            if (started && cy.g >= gend) continue;                     // an earlier window decoded it
+            if (!started || cy.g < 2 * 64 * blk) {
+                cy = vcursor_block(Y.L->bytes, yb0, yb1, Y.n, blk, __builtin_amdgcn_readlane(bv, jl),
+                                   __builtin_amdgcn_readlane(bp, jl));
+                started = true;
+            }
+            const uint32_t r = scan_windows<TILE>(cy, gend, te, x_lo, x_hi, ys, ye, lane);
+            if (r) return r == 1;
+        }
     }
     return false;
 }

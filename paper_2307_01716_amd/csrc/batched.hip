@@ -283,52 +283,136 @@ __device__ __forceinline__ void load_resident(const Resident &x, const uint32_t 
 // ((e - 1) >> sh) + 1), mapped elements staying sorted by start and by end
 // (they may touch or overlap each other), which is all the scan needs.
 constexpr int kAsIs = 0, kShifted = 1;
+
+// After this many chunks a stream skips the chunks that cannot meet the
+// resident list (512-interval instances; see stream_piece).
+constexpr uint32_t kSkipChunks = 4;
+
+// The chunks of Y from jj (64 * C elements) against the resident list:
+// 0 = go on, 1 = the scan's answer is true, 2 = the chunk starts at or
+// after the piece's end (and so do all later ones).
+template <int TILE, int C, bool FA, int MAP>
+__device__ __forceinline__ uint32_t stream_chunk(const Resident &x, const uint32_t *__restrict__ ys,
+                                                 const uint32_t *__restrict__ ye, uint32_t jj, uint32_t m,
+                                                 uint32_t stop, uint32_t lane, bool *th, uint32_t sh, bool &any) {
+    uint32_t s[C], e[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        // lanes past the end load nothing and take an empty [0, 0)
+        const uint32_t k = jj + c * 64 + lane;
+        s[c] = k < m ? gload(ys, k) : 0u;
+        e[c] = k < m ? gload(ye, k) : 0u;
+        if (MAP == kShifted) {
+            s[c] >>= sh;
+            e[c] = k < m ? ((e[c] - 1) >> sh) + 1 : 0u;
+        }
+    }
+    // this chunk and all later ones start at or after the piece's end
+    if (uniform(s[0]) >= stop) return 2;
+    bool hit = false, f = false;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        if (FA) {
+            // the F search runs beside the A search; its answer counts
+            // only where the element overlaps the A-list
+            const uint32_t *pa, *pf;
+            lds_first_above2<TILE>(x.ae, x.fe, s[c], pa, pf);
+            const uint32_t sa = pa[TILE], sf = pf[TILE];
+            const bool h = sa < e[c];
+            hit |= h;
+            f |= h & (sf < e[c]);
+        } else {
+            hit |= lds_first_above<TILE>(x.ae, s[c])[TILE] < e[c];
+        }
+    }
+    if (__any(hit)) {
+        if (!FA) return 1;
+        any = true;
+        if (__any(f)) {
+            *th = true;
+            return 1;
+        }
+    }
+    return 0;
+}
+
 template <int TILE, int C, bool FA, int MAP>
 __device__ __forceinline__ bool stream_piece(const Resident &x, const uint32_t *__restrict__ ys,
                                              const uint32_t *__restrict__ ye, uint32_t j, uint32_t m,
                                              uint32_t stop, uint32_t lane, bool *th, uint32_t sh) {
     bool any = false;
-    for (; j < m; j += 64 * C) {
-        uint32_t s[C], e[C];
+    if constexpr (TILE < 512 || MAP != kAsIs) {
+        for (; j < m; j += 64 * C) {
+            uint32_t s[C], e[C];
 #pragma unroll
-        for (int c = 0; c < C; c++) {
-            // lanes past the end load nothing and take an empty [0, 0)
-            const uint32_t k = j + c * 64 + lane;
-            s[c] = k < m ? gload(ys, k) : 0u;
-            e[c] = k < m ? gload(ye, k) : 0u;
-            if (MAP == kShifted) {
-                s[c] >>= sh;
-                e[c] = k < m ? ((e[c] - 1) >> sh) + 1 : 0u;
+            for (int c = 0; c < C; c++) {
+                // lanes past the end load nothing and take an empty [0, 0)
+                const uint32_t k = j + c * 64 + lane;
+                s[c] = k < m ? gload(ys, k) : 0u;
+                e[c] = k < m ? gload(ye, k) : 0u;
+                if (MAP == kShifted) {
+                    s[c] >>= sh;
+                    e[c] = k < m ? ((e[c] - 1) >> sh) + 1 : 0u;
+                }
             }
-        }
-        // this chunk and all later ones start at or after the piece's end
-        if (uniform(s[0]) >= stop) break;
-        bool hit = false, f = false;
+            // this chunk and all later ones start at or after the piece's end
+            if (uniform(s[0]) >= stop) break;
+            bool hit = false, f = false;
 #pragma unroll
-        for (int c = 0; c < C; c++) {
-            if (FA) {
-                // the F search runs beside the A search; its answer counts
-                // only where the element overlaps the A-list
-                const uint32_t *pa, *pf;
-                lds_first_above2<TILE>(x.ae, x.fe, s[c], pa, pf);
-                const uint32_t sa = pa[TILE], sf = pf[TILE];
-                const bool h = sa < e[c];
-                hit |= h;
-                f |= h & (sf < e[c]);
-            } else {
-                hit |= lds_first_above<TILE>(x.ae, s[c])[TILE] < e[c];
+            for (int c = 0; c < C; c++) {
+                if (FA) {
+                    // the F search runs beside the A search; its answer counts
+                    // only where the element overlaps the A-list
+                    const uint32_t *pa, *pf;
+                    lds_first_above2<TILE>(x.ae, x.fe, s[c], pa, pf);
+                    const uint32_t sa = pa[TILE], sf = pf[TILE];
+                    const bool h = sa < e[c];
+                    hit |= h;
+                    f |= h & (sf < e[c]);
+                } else {
+                    hit |= lds_first_above<TILE>(x.ae, s[c])[TILE] < e[c];
+                }
+            }
+            if (__any(hit)) {
+                if (!FA) return true;
+                any = true;
+                if (__any(f)) {
+                    *th = true;
+                    return true;
+                }
             }
         }
-        if (__any(hit)) {
-            if (!FA) return true;
-            any = true;
-            if (__any(f)) {
-                *th = true;
-                return true;
-            }
+        return any;
+    } else {
+        constexpr uint32_t CH = 64 * C;
+        for (uint32_t n = 0; j < m && n < kSkipChunks; j += CH, n++) {
+            const uint32_t r = stream_chunk<TILE, C, FA, MAP>(x, ys, ye, j, m, stop, lane, th, sh, any);
+            if (r == 1) return true;
+            if (r == 2) return any;
         }
+        // The rest of a long stream is taken 64 chunks at a time: lane l
+        // tests chunk l, whose elements lie in [its first start, the next
+        // chunk's first start) (Y is sorted and disjoint); only a resident
+        // interval meeting that range can meet one of them (with FA, an F
+        // overlap needs an A overlap: F lies inside A), so only the chunks
+        // that pass are read.
+        for (uint32_t q0 = j; q0 < m; q0 += 64 * CH) {
+            const uint32_t cj = q0 + lane * CH;
+            const bool in = cj < m;
+            const uint32_t cs = in ? gload(ys, cj) : 0xffffffffu;
+            const uint32_t cn = cj + CH < m ? gload(ys, cj + CH) : 0xffffffffu;
+            const bool need = in && cs < stop && lds_first_above<TILE>(x.ae, cs)[TILE] < cn;
+            uint64_t mask = __ballot(need);
+            const bool past = __any(in && cs >= stop);   // from that chunk on, past the piece's end
+            while (mask) {
+                const uint32_t jj = q0 + uint32_t(__builtin_ctzll(mask)) * CH;
+                mask &= mask - 1;
+                if (stream_chunk<TILE, C, FA, MAP>(x, ys, ye, jj, m, stop, lane, th, sh, any) == 1) return true;
+            }
+            if (past) break;
+        }
+        return any;
     }
-    return any;
 }
 
 // Does every element of Y[j..m) that starts below `stop` lie inside one

@@ -641,46 +641,88 @@ struct WgShared {
 
 constexpr uint32_t kHitAA = 1, kHitTH = 2;
 
+// One chunk of a workgroup pass (see wg_stream), from Y[j]: true when the
+// wave's pass ends there (the end of Y, a chunk starting at or after
+// `stop`, or a true hit, its own or another wave's).
+template <int TW, int C, bool FA>
+__device__ __forceinline__ bool wg_chunk(const Resident &x, const uint32_t *__restrict__ ys,
+                                         const uint32_t *__restrict__ ye, uint32_t j, uint32_t m, uint32_t stop,
+                                         uint32_t lane, WgShared *sh) {
+    if (j >= m) return true;
+    if (uniform(__hip_atomic_load(&sh->bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) & kHitTH) return true;
+    uint32_t s[C], e[C];
+#pragma unroll
+    for (int q = 0; q < C; q++) {
+        const uint32_t k = j + q * 64 + lane;
+        s[q] = k < m ? gload(ys, k) : 0u;
+        e[q] = k < m ? gload(ye, k) : 0u;
+    }
+    if (uniform(s[0]) >= stop) return true;
+    bool hit = false, f = false;
+#pragma unroll
+    for (int q = 0; q < C; q++) {
+        if (FA) {
+            const uint32_t *pa, *pf;
+            lds_first_above2<TW>(x.ae, x.fe, s[q], pa, pf);
+            const bool h = pa[TW] < e[q];
+            hit |= h;
+            f |= h & (pf[TW] < e[q]);
+        } else {
+            hit |= lds_first_above<TW>(x.ae, s[q])[TW] < e[q];
+        }
+    }
+    const bool any_hit = __any(hit);
+    const bool th = FA ? (any_hit && __any(f)) : any_hit;
+    if (any_hit && lane == 0)
+        __hip_atomic_fetch_or(&sh->bits, th ? (kHitAA | kHitTH) : kHitAA, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
+    return th;
+}
+
 // One pass of the workgroup over Y[j0, m) against the resident tile, up to
 // the first chunk starting at or after `stop`.  FA: the pass over Y.A (an
 // A-list overlap sets kHitAA; one that also meets X.F sets kHitTH); else
-// the pass over Y.F (an overlap with X.A sets kHitTH).
+// the pass over Y.F (an overlap with X.A sets kHitTH).  Wave w takes chunks
+// w, w + 4, ...: its first kSkipChunks one by one, then 64 of them at a
+// time, lane l testing the wave's l-th next chunk (its elements lie between
+// its first start and the next chunk's), and reading only the chunks a
+// resident interval can meet.  The chunk at which the wave stops (its first
+// chunk past Y's end or starting at or after `stop`, whether read or only
+// tested) goes to cstop either way.
 template <int TW, int C, bool FA>
 __device__ __forceinline__ void wg_stream(const Resident &x, const uint32_t *__restrict__ ys,
                                           const uint32_t *__restrict__ ye, uint32_t j0, uint32_t m,
                                           uint32_t stop, uint32_t w, uint32_t lane, WgShared *sh) {
+    constexpr uint32_t CH = 64 * C;
     uint32_t c = w;
-    for (;; c += kWavesPerBlock) {
-        const uint32_t j = j0 + c * (64 * C);
-        if (j >= m) break;
+    bool done = false;
+    for (uint32_t n = 0; n < kSkipChunks && !done; n++) {
+        done = wg_chunk<TW, C, FA>(x, ys, ye, j0 + c * CH, m, stop, lane, sh);
+        if (!done) c += kWavesPerBlock;
+    }
+    while (!done) {
         if (uniform(__hip_atomic_load(&sh->bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) & kHitTH) break;
-        uint32_t s[C], e[C];
-#pragma unroll
-        for (int q = 0; q < C; q++) {
-            const uint32_t k = j + q * 64 + lane;
-            s[q] = k < m ? gload(ys, k) : 0u;
-            e[q] = k < m ? gload(ye, k) : 0u;
-        }
-        if (uniform(s[0]) >= stop) break;
-        bool hit = false, f = false;
-#pragma unroll
-        for (int q = 0; q < C; q++) {
-            if (FA) {
-                const uint32_t *pa, *pf;
-                lds_first_above2<TW>(x.ae, x.fe, s[q], pa, pf);
-                const bool h = pa[TW] < e[q];
-                hit |= h;
-                f |= h & (pf[TW] < e[q]);
-            } else {
-                hit |= lds_first_above<TW>(x.ae, s[q])[TW] < e[q];
+        const uint32_t cj = j0 + (c + lane * kWavesPerBlock) * CH;   // this lane's chunk
+        const bool in = cj < m;
+        const uint32_t cs = in ? gload(ys, cj) : 0xffffffffu;
+        const uint32_t cn = cj + CH < m ? gload(ys, cj + CH) : 0xffffffffu;
+        const bool need = in && cs < stop && lds_first_above<TW>(x.ae, cs)[TW] < cn;
+        const uint64_t ends = __ballot(!in || cs >= stop);   // the wave's pass ends at the first of these
+        uint64_t mask = __ballot(need);                      // all below it: starts increase with the chunk
+        while (mask && !done) {
+            const uint32_t l = uint32_t(__builtin_ctzll(mask));
+            mask &= mask - 1;
+            if (wg_chunk<TW, C, FA>(x, ys, ye, j0 + (c + l * kWavesPerBlock) * CH, m, stop, lane, sh)) {
+                c += l * kWavesPerBlock;
+                done = true;
             }
         }
-        const bool any_hit = __any(hit);
-        const bool th = FA ? (any_hit && __any(f)) : any_hit;
-        if (any_hit && lane == 0)
-            __hip_atomic_fetch_or(&sh->bits, th ? (kHitAA | kHitTH) : kHitAA, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (th) break;
+        if (done) break;
+        if (ends) {
+            c += uint32_t(__builtin_ctzll(ends)) * kWavesPerBlock;
+            break;
+        }
+        c += 64 * kWavesPerBlock;
     }
     if (lane == 0) __hip_atomic_fetch_min(&sh->cstop, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }

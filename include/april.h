@@ -236,8 +236,7 @@ typedef struct {
                               128, 256 or 512 (0 = 256 when the two collections' A-lists
                               average at most 256 intervals, else 512; compressed lists:
                               256, 512, 1024, 0 = 512) */
-    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2,
-                              or 4 with 512-interval tiles);
+    uint32_t chunk;        /* batched: streamed intervals per lane per step: 1, 2 or 4 (0 = 2);
                               compressed lists: decoding windows (up to 130 intervals each) in
                               the first tile of each join, 1 to 4, capped at the tile (0 = 1) */
     uint32_t thread_max;   /* batched: pairs whose four lists all have at most this many

@@ -1207,9 +1207,10 @@ static void set_wg_bin(BatchArgs &b, uint32_t wg_min, void *workspace) {
 int launch_batched(const FilterArgs &a, const april_filter_opts_t &o, int cus, void *workspace,
                    hipStream_t stream) {
     const uint32_t tile = o.tile ? o.tile : 256;
-    // default chunk: 2 elements per lane per step, 4 with 512-interval tiles
-    // (long lists; the skewed workload ran 72.1 against 75.4 ms)
-    const uint32_t chunk = o.chunk ? o.chunk : tile >= 512 ? 4 : 2;
+    // default chunk: 2 elements per lane per step (with chunk skipping, also
+    // the best for 512-interval tiles: skewed workload 61.5 against 64.5 ms
+    // with 4, partitioned raw join 118.5 against 123.5 ms)
+    const uint32_t chunk = o.chunk ? o.chunk : 2;
     BatchArgs b;
     b.f = a;
     b.xhead = static_cast<unsigned int *>(workspace);

@@ -4,15 +4,17 @@
 // One wavefront per pair, pairs taken 64 at a time from per-XCD contiguous
 // ranges like the raw batched schedule.  The three joins of Alg. 2 run in
 // order: X.A x Y.A, then X.A x Y.F and X.F x Y.A.  X is the R object when its
-// lists fit the wave's decode cache: it is decoded once, into the cache, for
-// a run of pairs that share it, and each join copies its tiles from there
-// into LDS (skipping the copy when LDS already holds that tile).  Otherwise X
-// is the side with the shorter lists, decoded tile by tile into LDS by each
-// join.  For each tile, the Y intervals that can meet it are decoded window by
-// window into a small LDS buffer: from the last block whose first start is at
-// or before the tile's first start, until a Y start reaches the tile's end.
-// Every lane binary-searches the tile for its Y intervals (the overlap test of
-// the raw batched kernel).  A ballot after each window ends the join early.
+// lists fit the wave's decode cache: its A-list is decoded once, into the
+// cache, for a run of pairs that share it (its F-list when a X.F x Y.A join
+// first needs it, which few pairs reach), and each join copies its tiles
+// from there into LDS (skipping the copy when LDS already holds that tile).
+// Otherwise X is the side with the shorter lists, decoded tile by tile into
+// LDS by each join.  Tiles are padded to TILE entries.  For each tile, the Y
+// intervals that can meet it are decoded window by window into a small LDS
+// buffer: a short Y from its start; a longer one only in the 64-interval
+// blocks (from its block index) whose key range meets a tile interval.
+// Every lane searches the tile for its Y intervals (the overlap test of the
+// raw batched kernel).  A ballot after each window ends the join early.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -280,7 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
     const uint32_t cap = a.cache ? a.cache_cap : 0u;
     uint32_t *cas = a.cache + uint64_t(blockIdx.x * kWavesPerBlock + w) * 4 * cap;
     uint32_t *cae = cas + cap, *cfs = cae + cap, *cfe = cfs + cap;
-    uint32_t cached = 0xffffffffu;   // the R object held there
+    uint32_t cached = 0xffffffffu;   // the R object whose A-list is held there
+    bool cached_f = false;           // its F-list too (decoded when a FA join first needs it)
     uint32_t held = kNoTile;         // its tile in ts/te
     const uint32_t my_xcd = blockIdx.x % a.xcds;
     for (uint32_t k = 0; k < a.xcds; k++) {
@@ -315,18 +318,28 @@ __global__ __launch_bounds__(kBlock) void k_filter_vbyte(CArgs a) {
                     // pairs share it), S streamed
                     if (r != cached) {
                         decode_all(ListRef{&pa->Ar, r, nar}, cas, cae, lane);
-                        decode_all(ListRef{&pa->Fr, r, nfr}, cfs, cfe, lane);
                         __threadfence_block();   // the wave's stores, visible to all its lanes
                         cached = r;
+                        cached_f = false;
                         held = kNoTile;
                     }
                     const ListRef SA{&pa->As, s, nas}, SF{&pa->Fs, s, nfs};
-                    if (!rjoin<TILE>(cas, cae, nar, 0, &held, SA, ts, te, ys, ye, a.search_min, lane))
+                    if (!rjoin<TILE>(cas, cae, nar, 0, &held, SA, ts, te, ys, ye, a.search_min, lane)) {
                         v = APRIL_TN;
-                    else if (rjoin<TILE>(cas, cae, nar, 0, &held, SF, ts, te, ys, ye, a.search_min, lane) ||
-                             rjoin<TILE>(cfs, cfe, nfr, 1, &held, SA, ts, te, ys, ye, a.search_min, lane))
+                    } else if (rjoin<TILE>(cas, cae, nar, 0, &held, SF, ts, te, ys, ye, a.search_min, lane)) {
                         v = APRIL_TH;
-                    else v = APRIL_INDECISIVE;
+                    } else {
+                        // the FA join, which few pairs reach: R's F-list is
+                        // decoded into the cache on first use
+                        if (!cached_f) {
+                            decode_all(ListRef{&pa->Fr, r, nfr}, cfs, cfe, lane);
+                            __threadfence_block();
+                            cached_f = true;
+                        }
+                        v = rjoin<TILE>(cfs, cfe, nfr, 1, &held, SA, ts, te, ys, ye, a.search_min, lane)
+                                ? APRIL_TH
+                                : APRIL_INDECISIVE;
+                    }
                     if (lane == 0) {
                         a.verdict[p] = v;
                         c_tn += v == APRIL_TN;

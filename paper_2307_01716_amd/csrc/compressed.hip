@@ -242,8 +242,14 @@ __device__ bool rjoin(const uint32_t *xs, const uint32_t *xe, uint32_t nx, uint3
                       const ListRef &Y, uint32_t *ts, uint32_t *te, uint32_t *ys, uint32_t *ye,
                       uint32_t search_min, uint32_t lane) {
     if (nx == 0 || Y.n == 0) return false;
-    // tiles of TILE - 1 intervals, so that every tile has a padding entry
-    for (uint32_t t0 = 0; t0 < nx; t0 += TILE - 1) {
+    // tiles of TILE - 1 intervals, so that every tile has a padding entry;
+    // any order finds an overlap, so the join starts with the tile LDS
+    // already holds (where the previous join on this list stopped) and
+    // wraps around
+    const uint32_t ntiles = (nx + TILE - 2) / (TILE - 1);
+    const uint32_t first = (*held != kNoTile && (*held & 1u) == list) ? (*held >> 1) / (TILE - 1) : 0u;
+    for (uint32_t n = 0; n < ntiles; n++) {
+        const uint32_t t0 = (first + n < ntiles ? first + n : first + n - ntiles) * (TILE - 1);
         const uint32_t nt = min(uint32_t(TILE - 1), nx - t0);
         const uint32_t key = (t0 << 1) | list;
         if (*held != key) {

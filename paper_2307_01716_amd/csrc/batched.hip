@@ -554,7 +554,7 @@ __device__ __forceinline__ uint32_t join_piece(const Resident &res, const PairLi
 // with the same `key`; otherwise X is loaded piece by piece.
 template <int TILE, int C, int MODE>
 __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, const PairLists &L,
-                              uint32_t search_min, uint32_t lane, uint32_t sh) {
+                              uint32_t search_min, uint32_t lane, uint32_t sh, uint32_t &pcached, uint32_t *pw) {
     if (L.nxa == 0 || L.nya == 0) return APRIL_TN;
     if (L.nxa < TILE && L.nxf < TILE) {
         if (key != cached) {
@@ -564,6 +564,7 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
             res.na = L.nxa;
             res.nf = L.nxf;
             cached = key;
+            pcached = kNone;
         }
         const uint32_t j = join_piece<TILE, C, MODE>(res, L, 0, kNone, search_min, lane, sh, 3);
         if (MODE == kWithinJoin) return !(j & 1) ? APRIL_TN : (j & 2) ? APRIL_TH : APRIL_INDECISIVE;
@@ -572,6 +573,21 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
     cached = kNone;
     bool aa = false, in = true;   // (within joins: every piece so far has A(r) inside F(s))
     uint32_t a0 = 0, f0 = 0, k0 = 0;
+    // 512-interval Alg. 2 instance: the piece the previous pair left resident,
+    // when it belongs to this object, is joined first (any order of pieces
+    // finds an overlap, and consecutive pairs sharing an object tend to meet
+    // it in the same place), then skipped in the walk below; its bounds are
+    // in the wave's words pw (a0, a1, f0, f1, k0, k1)
+    constexpr bool kHold = TILE >= 512 && MODE == kAlg2;
+    uint32_t held_a0 = kNone;
+    if constexpr (kHold) {
+        if (pcached == key) {
+            const uint32_t j = join_piece<TILE, C, MODE>(res, L, uniform(pw[4]), uniform(pw[5]), search_min, lane, sh, 3);
+            if (j == 1) return APRIL_TH;
+            aa |= j == 2;
+            held_a0 = uniform(pw[0]);
+        }
+    }
     for (;;) {
         // at most TILE - 1 A elements from a0; the range ends where the next
         // one starts; then at most TILE - 1 F elements
@@ -586,11 +602,26 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
             k1 = uniform(gload(L.xfs, f1));
             a1 = a0 + uniform(wave_first_above(L.xas + a0, a1 - a0, k1 - 1, lane));
         }
+        if (kHold && a0 == held_a0) {
+            // the held piece, joined above
+        } else {
         wave_lds_sync();
         load_resident<TILE>(res, L.xas + a0, L.xae + a0, a1 - a0, L.xfs + f0, L.xfe + f0, f1 - f0, lane);
         wave_lds_sync();
         res.na = a1 - a0;
         res.nf = f1 - f0;
+        if constexpr (kHold) {
+            // this piece is resident now
+            if (lane == 0) {
+                pw[0] = a0;
+                pw[1] = a1;
+                pw[2] = f0;
+                pw[3] = f1;
+                pw[4] = k0;
+                pw[5] = k1;
+            }
+            pcached = key;
+        }
         if (MODE == kWithinJoin) {
             const uint32_t j =
                 join_piece<TILE, C, MODE>(res, L, k0, k1, search_min, lane, sh, (aa ? 0u : 1u) | (in ? 2u : 0u));
@@ -601,6 +632,7 @@ __device__ uint32_t wave_pair(Resident &res, uint32_t &cached, uint32_t key, con
             const uint32_t j = join_piece<TILE, C, MODE>(res, L, k0, k1, search_min, lane, sh, 3);
             if (j == 1) return APRIL_TH;
             aa |= j == 2;
+        }
         }
         if (k1 == kNone) break;
         // next piece: the first elements that end above k1
@@ -964,6 +996,8 @@ void k_batched(BatchArgs b) {
     res.fs = res.fe + TILE;
     res.na = res.nf = 0;
     uint32_t cached = kNone;   // resident object id | side bit
+    uint32_t pcached = kNone;  // object whose piece is resident (512-interval Alg. 2 instance)
+    __shared__ uint32_t piece_words[kWavesPerBlock][8];
 
     // ---- pairs in input order: each XCD drains its own contiguous range,
     // then helps the others
@@ -1038,7 +1072,8 @@ void k_batched(BatchArgs b) {
                 const PairLists L = lane_pair(m, k2);
                 const uint32_t kk = lane_val(key, k2);
                 const uint32_t sh = MODE == kMixedOrders ? ((kk & kSideS) ? pb->shift_r : pb->shift_s) : 0;
-                const uint32_t v = wave_pair<TILE, C, MODE>(res, cached, kk, L, search_min, lane, sh);
+                const uint32_t v =
+                    wave_pair<TILE, C, MODE>(res, cached, kk, L, search_min, lane, sh, pcached, piece_words[w]);
                 vv = lane == k2 ? v : vv;
             }
             // very short lists: every such lane runs Alg. 2 on its own pair
